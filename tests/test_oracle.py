@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+elementwise definitions written as loops, library SVD/QR, closed forms of the
+ALS iteration (Appendix A), exact recovery, the st-HOSVD error identity and
+the bounds of Lemma 2 / Theorem 4, finite differences, published generator
+outputs.  No GPU needed.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import tucker_oracle as o
+from workloads import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- P1: TTM
+
+def _ttm_loops(A, M, n):
+    """Mode-n product by the elementwise definition of Section 2."""
+    shape = list(A.shape)
+    shape[n] = M.shape[0]
+    out = np.zeros(shape)
+    for idx in np.ndindex(*shape):
+        s = 0.0
+        for i in range(A.shape[n]):
+            src = list(idx)
+            src[n] = i
+            s += A[tuple(src)] * M[idx[n], i]
+        out[idx] = s
+    return out
+
+
+@pytest.mark.parametrize("dims", [(2, 3, 4), (3, 1, 5, 2)])
+def test_ttm_matches_elementwise_definition(dims):
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal(dims)
+    for n in range(len(dims)):
+        M = rng.standard_normal((3, dims[n]))
+        np.testing.assert_allclose(o.ttm(A, M, n), _ttm_loops(A, M, n),
+                                   rtol=0, atol=1e-14)
+
+
+def test_unfold_fold_roundtrip_and_paper_order():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((3, 4, 2, 5))
+    for n in range(4):
+        U = o.unfold(A, n)
+        np.testing.assert_array_equal(o.fold(U, n, A.shape), A)
+        Up = o.unfold_paper(A, n)
+        # same multiset of columns: the orders differ only by a permutation
+        assert sorted(map(tuple, U.T.round(12))) == sorted(map(tuple, Up.T.round(12)))
+        # left singular subspace and Gram do not depend on the column order
+        np.testing.assert_allclose(U @ U.T, Up @ Up.T, atol=1e-13)
+        # element (i_n, j) placement by the explicit column-major formula
+        for idx in np.ndindex(*A.shape):
+            j, stride = 0, 1
+            for k in range(4):
+                if k != n:
+                    j += idx[k] * stride
+                    stride *= A.shape[k]
+            assert Up[idx[n], j] == A[idx]
+
+
+def test_ttm_identity_composition_commutation():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 5, 6))
+    np.testing.assert_allclose(o.ttm(A, np.eye(5), 1), A, atol=1e-15)
+    M1 = rng.standard_normal((3, 5))
+    M2 = rng.standard_normal((2, 3))
+    np.testing.assert_allclose(o.ttm(o.ttm(A, M1, 1), M2, 1),
+                               o.ttm(A, M2 @ M1, 1), atol=1e-13)
+    P = rng.standard_normal((2, 4))
+    np.testing.assert_allclose(o.ttm(o.ttm(A, M1, 1), P, 0),
+                               o.ttm(o.ttm(A, P, 0), M1, 1), atol=1e-13)
+
+
+# --------------------------------------------- generator (published outputs)
+
+def test_splitmix64_reference_outputs():
+    with open(os.path.join(GOLDEN, "splitmix64.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for row in rows:
+        seed = int(row[0])
+        want = [int(x, 16) for x in row[1:]]
+        assert o.splitmix_stream(seed, len(want)) == want
+        # the vectorised counter form gives the same stream
+        got = o.splitmix_uniform(seed, np.arange(len(want)))
+        np.testing.assert_array_equal(
+            got, np.array([(w >> 40) * 2.0 ** -24 for w in want]))
+
+
+def test_sketch_is_uniform_dense_full_rank():
+    S = o.init_sketch(7, 2, 5000, 20)
+    assert S.min() >= 0.0 and S.max() < 1.0
+    assert abs(S.mean() - 0.5) < 0.01 and abs(S.var() - 1 / 12) < 0.005
+    assert np.linalg.matrix_rank(S) == 20
+    # values are exact multiples of 2^-24 (representable in float32)
+    np.testing.assert_array_equal(S, S.astype(np.float32).astype(np.float64))
+    # distinct modes draw distinct sketches
+    assert not np.allclose(S, o.init_sketch(7, 3, 5000, 20))
+
+
+# ------------------------------------------------- P2: SVD-based HOSVDs
+
+def test_exact_recovery_svd_hosvd():
+    rng = np.random.default_rng(4)
+    A, A0, G, Us = synth.tucker_lowrank(rng, (12, 10, 9), (3, 4, 2), 0.0)
+    for res in (o.thosvd_svd(A, (3, 4, 2)), o.sthosvd_svd(A, (3, 4, 2))[0]):
+        assert o.relerr(A, res.G, res.U) <= 1e-13
+
+
+def test_svd_methods_agree_with_eig():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((10, 8, 6))
+    a = o.thosvd_svd(A, (4, 3, 2), method="svd")
+    b = o.thosvd_svd(A, (4, 3, 2), method="eig")
+    for Ua, Ub in zip(a.U, b.U):
+        assert o.subspace_distance(Ua, Ub) < 1e-10
+
+
+def test_sthosvd_error_identity_and_bounds():
+    """st-HOSVD: ||A - A_hat||^2 equals the sum of the discarded squared
+    singular values of the successive B_(n) (the successive projections are
+    orthogonal; Lemma 2's reference).  t-HOSVD error^2 <= sum gamma_n
+    (eq. E5.1); the optimum is bounded below by max gamma_n."""
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((9, 8, 7, 6))
+    ranks = (4, 3, 5, 2)
+    st, disc = o.sthosvd_svd(A, ranks, order=[2, 0, 3, 1])
+    err2 = o.relerr(A, st.G, st.U) ** 2 * o.frob(A) ** 2
+    assert abs(err2 - sum(disc)) <= 1e-10 * o.frob(A) ** 2
+    gam = o.tail_energies(A, ranks)
+    t = o.thosvd_svd(A, ranks)
+    et2 = o.relerr(A, t.G, t.U) ** 2 * o.frob(A) ** 2
+    assert et2 <= sum(gam) * (1 + 1e-12)
+    assert err2 <= sum(gam) * (1 + 1e-12)
+    assert min(err2, et2) >= max(gam) * (1 - 1e-12)
+
+
+# ------------------------------------------- P3: the ALS iteration itself
+
+def test_als_closed_form_on_diagonal_matrix():
+    """Appendix A, eq. E2.5: for A = diag(sigma) the block ratio
+    T_k = L_k^(2) (L_k^(1))^{-1} evolves as T_{k+1} = S2^2 T_k S1^{-2}, hence
+    T_k[i,j] = (sigma_{r+i}/sigma_j)^{2k} T_0[i,j]."""
+    m, n, r = 7, 9, 3
+    sig = np.array([5.0, 4.0, 3.0, 2.0, 1.5, 1.0, 0.5])
+    A = np.zeros((m, n))
+    A[np.arange(m), np.arange(m)] = sig
+    rng = np.random.default_rng(7)
+    L = rng.standard_normal((m, r))
+    T0 = L[r:] @ np.linalg.inv(L[:r])
+    ratio = sig[r:, None] / sig[None, :r]
+    for k in range(1, 6):
+        R = o.als_r_update(A, L)
+        L = o.als_l_update(A, R)
+        Tk = L[r:] @ np.linalg.inv(L[:r])
+        np.testing.assert_allclose(Tk, ratio ** (2 * k) * T0, rtol=1e-9,
+                                   atol=1e-13)
+
+
+def test_als_r_update_is_least_squares_projection():
+    """Algorithm 3.3 R-update is the least-squares solution, so L R^T equals
+    the orthogonal projection of A onto span(L) (eq. E5.5), computed here
+    through an SVD basis of L."""
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((20, 30))
+    L = rng.standard_normal((20, 4))
+    R = o.als_r_update(A, L)
+    Ub = np.linalg.svd(L, full_matrices=False)[0]
+    np.testing.assert_allclose(L @ R.T, Ub @ (Ub.T @ A), atol=1e-12)
+    # L-update: least squares in the other factor
+    L2 = o.als_l_update(A, R)
+    Vb = np.linalg.svd(R, full_matrices=False)[0]
+    np.testing.assert_allclose(L2 @ R.T, (A @ Vb) @ Vb.T, atol=1e-12)
+
+
+def test_residual_trace_identity():
+    """For R the least-squares solution given L:
+    ||A - L R^T||^2 = ||A||^2 - tr(L^T L R^T R) (from eq. E5.5)."""
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((25, 40))
+    L = rng.standard_normal((25, 5))
+    R = o.als_r_update(A, L)
+    lhs = o.frob(A - L @ R.T) ** 2
+    rhs = o.frob(A) ** 2 - np.trace((L.T @ L) @ (R.T @ R))
+    assert abs(lhs - rhs) <= 1e-12 * o.frob(A) ** 2
+
+
+def test_als_converges_to_leading_subspace_with_gap():
+    """Theorem 2: with sigma_r > sigma_{r+1} the ALS subspace converges to
+    the leading left singular subspace (principal angles < 1e-6)."""
+    rng = np.random.default_rng(10)
+    U, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    V, _ = np.linalg.qr(rng.standard_normal((60, 40)))
+    s = np.concatenate([np.linspace(10, 6, 5), np.linspace(3, 0.1, 35)])
+    A = (U * s) @ V.T
+    L0 = o.als_initial_guess(A, o.init_sketch(0, 0, 60, 5))
+    res = o.als(A, 5, L0, tol=1e-15, max_iters=200, norm_ref=o.frob(A))
+    ang = o.principal_angles(res.L, U[:, :5])
+    assert np.max(ang) < 1e-6
+    # q-linear rate sigma_{r+1}^2/sigma_r^2 = 0.25: residual gaps shrink
+    d = np.abs(np.diff(res.residuals))
+    d = d[d > 1e-13]
+    assert len(d) >= 3 and np.all(d[2:] <= d[1:-1] * 0.5)
+
+
+def test_convergence_region_theorem3():
+    """Theorem 3: an initial guess with
+    ||L0^(2) (L0^(1))^{-1}||_2 below the bound converges."""
+    m, n, r = 8, 10, 3
+    sig = np.array([6.0, 5.0, 4.0, 2.0, 1.5, 1.0, 0.8, 0.5])
+    A = np.zeros((m, n))
+    A[np.arange(m), np.arange(m)] = sig
+    eps = 1.0
+    bound = np.sqrt((sig[r - 1] ** 2 - (sig[r - 1] - eps) ** 2)
+                    / ((sig[r - 1] - eps) ** 2 - sig[-1] ** 2))
+    rng = np.random.default_rng(11)
+    L1 = rng.standard_normal((r, r)) + 3 * np.eye(r)
+    T = rng.standard_normal((m - r, r))
+    T *= 0.99 * bound / np.linalg.norm(T, 2)
+    L0 = np.vstack([L1, T @ L1])
+    res = o.als(A, r, L0, tol=1e-15, max_iters=300, norm_ref=o.frob(A))
+    assert np.max(o.principal_angles(res.L, np.eye(m)[:, :r])) < 1e-6
+
+
+def test_init_exact_rank_gives_zero_residual():
+    """Section 5: R(L_0) lies in R(A_(n)); with exact rank r, L_0 already
+    spans the dominant subspace, res_0 = 0 and the stop test fires at k=1."""
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((30, 4)) @ rng.standard_normal((4, 50))
+    L0 = o.als_initial_guess(A, o.init_sketch(3, 0, 50, 4))
+    Ub = np.linalg.svd(A)[0][:, :4]
+    assert np.max(o.principal_angles(L0, Ub)) < 1e-12
+    res = o.als(A, 4, L0, tol=1e-4, max_iters=50, norm_ref=o.frob(A))
+    assert res.residuals[0] < 1e-12 * o.frob(A)
+    assert res.iters == 1 and res.converged
+
+
+def test_rank_deficient_raises():
+    """Remark 3: truncation above the numerical rank makes a Gram singular."""
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((20, 3)) @ rng.standard_normal((3, 30))
+    L0 = o.als_initial_guess(A, o.init_sketch(0, 0, 30, 5))
+    with pytest.raises(np.linalg.LinAlgError):
+        o.als(A, 5, L0, tol=1e-4, max_iters=5, norm_ref=o.frob(A))
+
+
+def test_not_converged_flag():
+    rng = np.random.default_rng(14)
+    A = rng.standard_normal((30, 40))
+    L0 = o.als_initial_guess(A, o.init_sketch(0, 0, 40, 6))
+    res = o.als(A, 6, L0, tol=1e-14, max_iters=2, norm_ref=o.frob(A))
+    assert res.iters == 2 and not res.converged and len(res.residuals) == 3
+
+
+# ------------------------------------------------------------- P6: QR
+
+def test_qr_signfix():
+    rng = np.random.default_rng(15)
+    L = rng.standard_normal((30, 6))
+    Q, R = o.qr_signfix(L)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(6), atol=1e-14)
+    assert np.all(np.diag(R) > 0)
+    np.testing.assert_allclose(Q @ R, L, atol=1e-13)
+    assert o.subspace_distance(Q, L) < 1e-13
+
+
+# --------------------------------------------------------- P7: drivers
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("order", [None, [2, 0, 1]])
+def test_sthosvd_als_identities(order):
+    """st-HOSVD-ALS: the literal truncation R_hat R^T equals B x_n U^T (checked
+    inside), ||A - A_hat||^2 = sum of the per-mode ALS residuals^2 and
+    Pythagoras ||A||^2 = ||G||^2 + ||A - A_hat||^2."""
+    rng = np.random.default_rng(16)
+    A = synth.tucker_lowrank(rng, (14, 12, 10), (5, 4, 3), 0.05)[0]
+    res = o.sthosvd_als(A, (5, 4, 3), order=order, tol=1e-6)
+    err2 = (o.relerr(A, res.G, res.U) * o.frob(A)) ** 2
+    assert _rel(err2, sum(i.resid ** 2 for i in res.info)) < 1e-10
+    assert _rel(o.frob(A) ** 2, o.frob(res.G) ** 2 + err2) < 1e-12
+    for U in res.U:
+        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-13)
+
+
+def test_thosvd_als_bounds():
+    """t-HOSVD-ALS: error^2 <= sum_n res_n^2 for orthonormal factors, and the
+    corrected Theorem 4 bound sqrt(sum (eta_n + sqrt(gamma_n)/||A||)^2)."""
+    rng = np.random.default_rng(17)
+    A = synth.tucker_lowrank(rng, (14, 12, 10), (5, 4, 3), 0.05)[0]
+    ranks = (5, 4, 3)
+    eta = 1e-3
+    res = o.thosvd_als(A, ranks, tol=eta)
+    nA = o.frob(A)
+    err = o.relerr(A, res.G, res.U)
+    assert (err * nA) ** 2 <= sum(i.resid ** 2 for i in res.info) * (1 + 1e-12)
+    gam = o.tail_energies(A, ranks)
+    # E5.0 is what Theorem 4 assumes; check it on the computed factors
+    for n in range(3):
+        ropt = np.sqrt(gam[n])
+        assert res.info[n].resid >= ropt * (1 - 1e-12)
+    bound = np.sqrt(sum((abs(i.resid - np.sqrt(g)) / nA + np.sqrt(g) / nA) ** 2
+                        for i, g in zip(res.info, gam)))
+    assert err <= bound * (1 + 1e-12)
+
+
+def test_als_matches_svd_at_tight_tolerance():
+    w = synth.workload_small_fp64()
+    A, ranks = w["A"], w["ranks"]
+    als_t = o.thosvd_als(A, ranks, tol=1e-12)
+    svd_t = o.thosvd_svd(A, ranks)
+    assert _rel(o.relerr(A, als_t.G, als_t.U), o.relerr(A, svd_t.G, svd_t.U)) < 1e-10
+    for Ua, Us in zip(als_t.U, svd_t.U):
+        assert np.max(o.principal_angles(Ua, Us)) < 1e-6
+    als_s = o.sthosvd_als(A, ranks, tol=1e-12)
+    svd_s = o.sthosvd_svd(A, ranks)[0]
+    assert _rel(o.relerr(A, als_s.G, als_s.U), o.relerr(A, svd_s.G, svd_s.U)) < 1e-10
+
+
+def test_full_rank_mode_is_identity():
+    rng = np.random.default_rng(18)
+    A = rng.standard_normal((4, 9, 8))
+    res = o.sthosvd_als(A, (4, 3, 5), tol=1e-6)
+    np.testing.assert_array_equal(res.U[0], np.eye(4))
+    assert res.info[0].iters == 0
+
+
+# ---------------------------------------------------------- P8: gradients
+
+def _fd(f, x, d, h=1e-3):
+    """Central difference at h and h/2 combined by Richardson extrapolation
+    (error O(h^4) instead of O(h^2))."""
+    c1 = (f(x + h * d) - f(x - h * d)) / (2 * h)
+    h2 = h / 2
+    c2 = (f(x + h2 * d) - f(x - h2 * d)) / (2 * h2)
+    return (4 * c2 - c1) / 3
+
+
+def test_tucker_loss_gradients_finite_difference():
+    rng = np.random.default_rng(19)
+    A = rng.standard_normal((7, 6, 5))
+    Us = [synth.orthonormal(rng, d, r) for d, r in zip(A.shape, (3, 2, 4))]
+    dA, dUs = o.tucker_loss_grads(A, Us)
+    D = rng.standard_normal(A.shape)
+    fd = _fd(lambda X: o.tucker_loss(X, Us), A, D)
+    assert _rel(np.sum(dA * D), fd) < 1e-8
+    for n in range(3):
+        Dn = rng.standard_normal(Us[n].shape)
+
+        def f(Un, n=n):
+            V = list(Us)
+            V[n] = Un
+            return o.tucker_loss(A, V)
+        assert _rel(np.sum(dUs[n] * Dn), _fd(f, Us[n], Dn)) < 1e-8
+    # at orthonormal factors dL/dA = 2E
+    E = A - o.tucker_to_tensor(o.project(A, Us), Us)
+    np.testing.assert_allclose(dA, 2 * E, atol=1e-12)
+
+
+def test_project_and_reconstruct_vjp_finite_difference():
+    rng = np.random.default_rng(20)
+    A = rng.standard_normal((6, 5, 4))
+    Us = [rng.standard_normal((d, r)) for d, r in zip(A.shape, (3, 2, 2))]
+    W = rng.standard_normal((3, 2, 2))
+    dA, dUs = o.project_vjp(A, Us, W)
+    f = lambda X: np.sum(o.project(X, Us) * W)
+    D = rng.standard_normal(A.shape)
+    assert _rel(np.sum(dA * D), _fd(f, A, D)) < 1e-8
+    for n in range(3):
+        Dn = rng.standard_normal(Us[n].shape)
+
+        def g(Un, n=n):
+            V = list(Us)
+            V[n] = Un
+            return np.sum(o.project(A, V) * W)
+        assert _rel(np.sum(dUs[n] * Dn), _fd(g, Us[n], Dn)) < 1e-8
+    G = rng.standard_normal((3, 2, 2))
+    Y = rng.standard_normal(A.shape)
+    dG, dU2 = o.reconstruct_vjp(G, Us, Y)
+    h = lambda X: np.sum(o.tucker_to_tensor(X, Us) * Y)
+    DG = rng.standard_normal(G.shape)
+    assert _rel(np.sum(dG * DG), _fd(h, G, DG)) < 1e-8
+    for n in range(3):
+        Dn = rng.standard_normal(Us[n].shape)
+
+        def k(Un, n=n):
+            V = list(Us)
+            V[n] = Un
+            return np.sum(o.tucker_to_tensor(G, V) * Y)
+        assert _rel(np.sum(dU2[n] * Dn), _fd(k, Us[n], Dn)) < 1e-8
+
+
+def test_loss_gradient_symmetry():
+    """The loss depends on U_n only through U_n U_n^T, so U_n^T dL/dU_n is
+    symmetric."""
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((7, 6, 5))
+    Us = [synth.orthonormal(rng, d, r) for d, r in zip(A.shape, (3, 2, 4))]
+    _, dUs = o.tucker_loss_grads(A, Us)
+    for U, dU in zip(Us, dUs):
+        M = U.T @ dU
+        np.testing.assert_allclose(M, M.T, atol=1e-12)

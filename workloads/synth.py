@@ -1,0 +1,159 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws random numbers and assembles test tensors; it computes
+none of the decomposition's results and holds no expected values.  Both the
+CPU oracle tests and the GPU path take their inputs from here.
+
+Recipe (noise is relative: the noise tensor E is rescaled so that
+||E||_F = rho * ||A0||_F exactly):
+
+* ``tucker_lowrank``: core of the given dims with i.i.d. N(0,1) entries times
+  an optional per-entry decay, factors U_n = Q of the QR of an I_n x R_n
+  Gaussian matrix, A = A0 + E.  Low multilinear rank signal plus noise, as in
+  the Tucker-model experiment of Section 6.1.2 (where the core is U[5,10] and
+  the noise absolute).
+* ``cp_lowrank``: the CP-model experiment of Section 6.1.1, lambda_r in
+  U[5,10] and unit-norm random vectors, plus relative noise.
+
+Seeds: ``2004025830 + k`` for the k-th named workload.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_BASE = 2004025830
+
+
+def rng_for(k: int) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + k)
+
+
+def orthonormal(rng: np.random.Generator, n: int, r: int) -> np.ndarray:
+    """Q factor of the QR decomposition of an n x r standard Gaussian."""
+    q, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    return q
+
+
+def _mode_product(X: np.ndarray, U: np.ndarray, n: int) -> np.ndarray:
+    # generator-side assembly of the synthetic signal (tensordot over mode n)
+    Y = np.tensordot(U, X, axes=([1], [n]))
+    return np.moveaxis(Y, 0, n)
+
+
+def decay_exp(shape, scale: float) -> np.ndarray:
+    """Per-entry factor exp(-(i1+...+iN)/scale), 0-based indices."""
+    idx = np.indices(shape).sum(axis=0)
+    return np.exp(-idx / scale)
+
+
+def decay_geom(shape, ratio: float) -> np.ndarray:
+    """Per-entry factor ratio^(i1+...+iN), 0-based indices."""
+    idx = np.indices(shape).sum(axis=0)
+    return ratio ** idx
+
+
+def tucker_lowrank(rng: np.random.Generator, dims, core_dims, noise_rel: float,
+                   decay: np.ndarray | None = None):
+    """A = G x_1 U_1 ... x_N U_N + E with ||E|| = noise_rel ||A0||.
+
+    Returns (A, A0, G, Us) in float64."""
+    G = rng.standard_normal(tuple(core_dims))
+    if decay is not None:
+        G = G * decay
+    Us = [orthonormal(rng, d, r) for d, r in zip(dims, core_dims)]
+    A0 = G
+    for n, U in enumerate(Us):
+        A0 = _mode_product(A0, U, n)
+    A = A0.copy()
+    if noise_rel > 0:
+        E = rng.standard_normal(A0.shape)
+        E *= noise_rel * np.linalg.norm(A0.ravel()) / np.linalg.norm(E.ravel())
+        A = A0 + E
+    return A, A0, G, Us
+
+
+def cp_lowrank(rng: np.random.Generator, dims, rank: int, noise_rel: float):
+    """Sum of ``rank`` rank-one terms lambda_r a_r o b_r o c_r (Section 6.1.1)
+    with lambda_r ~ U[5,10] and unit-norm Gaussian vectors, plus noise."""
+    lam = rng.uniform(5.0, 10.0, size=rank)
+    vecs = []
+    for d in dims:
+        V = rng.standard_normal((d, rank))
+        vecs.append(V / np.linalg.norm(V, axis=0, keepdims=True))
+    A0 = np.zeros(tuple(dims))
+    for r in range(rank):
+        t = lam[r]
+        for n, V in enumerate(vecs):
+            shp = [1] * len(dims)
+            shp[n] = dims[n]
+            t = t * V[:, r].reshape(shp)
+        A0 = A0 + t
+    A = A0.copy()
+    if noise_rel > 0:
+        E = rng.standard_normal(A0.shape)
+        E *= noise_rel * np.linalg.norm(A0.ravel()) / np.linalg.norm(E.ravel())
+        A = A0 + E
+    return A, A0
+
+
+def gaussian(rng: np.random.Generator, dims) -> np.ndarray:
+    return rng.standard_normal(tuple(dims))
+
+
+# ---------------------------------------------------------------------------
+# The five named workloads (small and full sizes)
+# ---------------------------------------------------------------------------
+
+def workload_small_fp64(k: int = 0):
+    """64x64x64, core 8^3 N(0,1), orthonormal 64x8 factors, 1e-3 relative
+    noise; ranks (8,8,8); tol 1e-8; float64."""
+    rng = rng_for(k)
+    A, A0, G, Us = tucker_lowrank(rng, (64, 64, 64), (8, 8, 8), 1e-3)
+    return dict(A=A, A0=A0, ranks=(8, 8, 8), tol=1e-8)
+
+
+def workload_4way(dims=(200, 200, 200, 200), R=20, noise_rel=1e-4, k: int = 1):
+    """Core R^4 with entries N(0,1) exp(-(i+j+k+l)/10), orthonormal I_n x R
+    factors, relative noise 1e-4 (4th-order decaying-core workload)."""
+    rng = rng_for(k)
+    core = (R,) * 4
+    A, A0, G, Us = tucker_lowrank(rng, dims, core, noise_rel,
+                                  decay=decay_exp(core, 10.0))
+    return dict(A=A, A0=A0, ranks=(R,) * 4)
+
+
+def workload_cube_geom(I=1024, C=64, R=48, noise_rel=1e-3, k: int = 2):
+    """Core C^3 with entries N(0,1) 0.9^(i+j+k), orthonormal I x C factors,
+    relative noise 1e-3; target ranks (R,R,R)."""
+    rng = rng_for(k)
+    core = (C,) * 3
+    A, A0, G, Us = tucker_lowrank(rng, (I,) * 3, core, noise_rel,
+                                  decay=decay_geom(core, 0.9))
+    return dict(A=A, A0=A0, ranks=(R,) * 3)
+
+
+def workload_autograd(I=256, R=32, k: int = 3):
+    """A i.i.d. N(0,1) of size I^3 and orthonormal I x R factors."""
+    rng = rng_for(k)
+    A = gaussian(rng, (I,) * 3)
+    Us = [orthonormal(rng, I, R) for _ in range(3)]
+    return dict(A=A, U=Us)
+
+
+def workload_batched(count=512, lo=16, hi=128, rlo=4, rhi=16, noise_rel=1e-3,
+                     k: int = 4):
+    """``count`` 3rd-order tensors with I_n ~ U{lo..hi} and R_n ~ U{rlo..rhi}
+    per mode, N(0,1) core of dims R_n times orthonormal factors plus 1e-3
+    relative noise.  Ranks are capped so each is a realisable multilinear
+    rank (R_n <= prod of the other two)."""
+    rng = rng_for(k)
+    items = []
+    for _ in range(count):
+        dims = tuple(int(x) for x in rng.integers(lo, hi + 1, size=3))
+        ranks = [int(x) for x in rng.integers(rlo, rhi + 1, size=3)]
+        for n in range(3):
+            others = ranks[(n + 1) % 3] * ranks[(n + 2) % 3]
+            ranks[n] = min(ranks[n], others, dims[n])
+        A, _, _, _ = tucker_lowrank(rng, dims, tuple(ranks), noise_rel)
+        items.append(dict(A=A, ranks=tuple(ranks)))
+    return items
