@@ -1,0 +1,219 @@
+"""Benchmark: st-HOSVD-ALS on one MI355X.
+
+Workload: 200x200x200x200 FP32 tensor, core 20^4 with entries
+N(0,1) exp(-(i+j+k+l)/10) times orthonormal 200x20 factors plus 1e-4 relative
+Gaussian noise (seeded, generated on the GPU); st-HOSVD-ALS to ranks
+(20,20,20,20) with eta = 1e-4.
+
+A step is one full st-HOSVD-ALS call (norm, initial sketches, every ALS sweep,
+QRs, the TTM truncations) on the resident input.  `value` is the step's
+algorithmic HBM bytes (one read of the current tensor per pass plus the TTM
+writes) divided by the step time.  The `roofline` object times the fused ALS
+sweep kernel alone on mode 1 (6.4 GB per launch) with HIP events on the stream
+it is launched on.  `cpu_baseline` times the FP64 CPU oracle's literal ALS
+sweeps on a sample of the mode-1 unfolding.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (200, 200, 200, 200)
+RANK = 20
+TOL = 1e-4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def step_bytes(dims, ranks, iters, elem=4):
+    """Algorithmic HBM bytes of one st-HOSVD-ALS call in natural order: the
+    norm of A, then per mode n on the current tensor B (s bytes): the norm of
+    B (n > 0), the initial sketch pass, iters+1 sweeps, and the truncation
+    (read s, write s*R_n/I_n)."""
+    cur = list(dims)
+    total = 0.0
+    size = float(elem)
+    for d in cur:
+        size *= d
+    total += size                      # ||A||
+    for n in range(len(dims)):
+        if n > 0:
+            total += size              # ||B||
+        total += size                  # sketch pass
+        total += (iters[n] + 1) * size  # sweeps
+        nxt = size * ranks[n] / cur[n]
+        total += size + nxt            # TTM read + write
+        cur[n] = ranks[n]
+        size = nxt
+    return total
+
+
+def relerr_gpu(tk, A, G, Us):
+    import torch
+    Ah = tk.tucker_reconstruct(G, Us)
+    e = torch.linalg.vector_norm((A.double() - Ah.double()).float()).item()
+    return e / torch.linalg.vector_norm(A.float()).item()
+
+
+def time_sweep_kernel(tk, A, Lq, launches=10):
+    """Average duration of the fused sweep kernel on mode 1, HIP events on
+    the stream the kernel is launched on (torch's current stream, which is
+    the stream handed to the library)."""
+    import torch
+    ws = tk.step_workspace(A, 0, Lq.shape[1])
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        tk.als_sweep_kernel(A, 0, Lq, reduce=False, workspace=ws)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(launches):
+        tk.als_sweep_kernel(A, 0, Lq, reduce=False, workspace=ws)
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / launches
+
+
+def cpu_baseline(A, ncols=2_000_000, sweeps=3):
+    """Literal Algorithm 3.3 sweeps of the FP64 oracle on the first ``ncols``
+    columns of the mode-1 unfolding (a 200 x ncols sample)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import tucker_oracle as o
+    An = A.reshape(A.shape[0], -1)[:, :ncols].double().cpu().numpy()
+    L0 = o.als_initial_guess(An, o.init_sketch(0, 0, An.shape[1], RANK))
+    t0 = time.perf_counter()
+    o.als(An, RANK, L0, tol=0.0, max_iters=sweeps - 1, norm_ref=o.frob(An))
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    gbs = sweeps * An.shape[0] * An.shape[1] * 4 / dt / 1e9
+    return dict(value=round(gbs, 4), unit="GB/s", cores=int(threads), kind="oracle",
+                sample=f"{sweeps} literal ALS sweeps (Alg. 3.3, explicit residual) of the "
+                       f"FP64 oracle on a 200 x {An.shape[1]} slice of the mode-1 unfolding; "
+                       f"{dt:.1f} s; bytes counted as FP32 (4 B/element) per sweep")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not "
+              "part of it (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2004_02583_amd as tk
+    from workloads import synth
+
+    tk.load_library()
+    dev = torch.device("cuda:0")
+    log("generating 200^4 FP32 workload on the GPU")
+    w = synth.workload_4way_torch(DIMS, RANK, 1e-4, device=dev)
+    A = w["A"]
+    ranks = w["ranks"]
+    torch.cuda.synchronize()
+    ws = torch.empty(tk.workspace_bytes("st", A.shape, A.dtype, ranks), dtype=torch.uint8,
+                     device=dev)
+
+    log("warmup")
+    info = None
+    for _ in range(args.warmup):
+        G, Us, info = tk.als_sthosvd(A, ranks, tol=TOL, workspace=ws)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    iters_seen = []
+    for _ in range(args.steps):
+        G, Us, info = tk.als_sthosvd(A, ranks, tol=TOL, workspace=ws)
+        iters_seen.append(tuple(info["iters"]))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    iters = list(iters_seen[-1])
+    nbytes = step_bytes(DIMS, ranks, iters)
+    value = nbytes / dt / 1e9
+    e32 = relerr_gpu(tk, A, G, Us)
+    log(f"fp32 step {dt*1e3:.2f} ms iters={iters} relerr={e32:.4e}")
+
+    log("fused sweep kernel timing")
+    Lq = Us[0].contiguous()
+    k_ms = time_sweep_kernel(tk, A, Lq)
+    sweep_bytes = A.numel() * A.element_size()
+    achieved = sweep_bytes / (k_ms * 1e-3) / 1e9
+
+    extra = {}
+    if not args.no_bf16:
+        log("bf16 storage time-to-tolerance")
+        Ab = A.to(torch.bfloat16)
+        wsb = torch.empty(tk.workspace_bytes("st", Ab.shape, Ab.dtype, ranks),
+                          dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            Gb, Ub, infob = tk.als_sthosvd(Ab, ranks, tol=TOL, workspace=wsb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Gb, Ub, infob = tk.als_sthosvd(Ab, ranks, tol=TOL, workspace=wsb)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - t0) / args.steps
+        eb = relerr_gpu(tk, A, Gb, Ub)
+        kb_ms = time_sweep_kernel(tk, Ab, Ub[0].contiguous())
+        extra = dict(bf16_ms_per_step=round(dtb * 1e3, 3), bf16_relerr=eb,
+                     bf16_iters=infob["iters"], bf16_sweep_kernel_ms=round(kb_ms, 4),
+                     bf16_speedup_vs_fp32=round(dt / dtb, 3))
+        del Ab, wsb
+        log(f"bf16 step {dtb*1e3:.2f} ms relerr={eb:.4e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(A)
+
+    out = {
+        "metric": "ALS sweep GB/s (% HBM peak); st-HOSVD time-to-tol vs plain FP32 at set error",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "st-HOSVD-ALS, 200^4 FP32, core 20^4 N(0,1)exp(-(i+j+k+l)/10) "
+                               "x orthonormal 200x20 factors + 1e-4 relative noise",
+                   "dims": list(DIMS), "ranks": list(ranks), "tol": TOL,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_fused (ALS sweep, mode 1, FP32)",
+                     "kernel_ms": round(k_ms, 4), "bytes_per_launch": sweep_bytes},
+        "cpu_baseline": cpu,
+        "iters": iters,
+        "relerr": e32,
+        "step_bytes": nbytes,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,834 @@
+// Host runtime and C ABI of libtucker_als: argument validation, workspace
+// carving, the per-mode ALS loop (Algorithm 3.3 with the stop test of
+// eq. E5.01), the t-/st-HOSVD-ALS drivers (Algorithms 3.4 / 3.5), TTM and
+// Tucker reconstruction (Section 2).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "tk_kernels.h"
+
+namespace tk {
+namespace {
+
+constexpr int NWG_MAX = 1024;     // upper bound on workgroups with partials
+constexpr size_t ALIGN = 256;
+
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+inline size_t dsize(int dt) { return dt == TK_F64 ? 8 : dt == TK_F32 ? 4 : 2; }
+inline int cdtype(int dt) { return dt == TK_F64 ? TK_F64 : TK_F32; }
+
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures.
+struct Arena {
+  char* base;
+  size_t cap, off;
+  bool ok;
+  Arena(void* b, size_t c) : base((char*)b), cap(c), off(0), ok(true) {}
+  void* take(size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    if (off > cap) ok = false;
+    return base ? (void*)(base + o) : nullptr;
+  }
+};
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    if ((x) != hipSuccess) return TK_ERR_HIP; \
+  } while (0)
+
+View mode_view(int N, const int64_t* dims, int n) {
+  View v;
+  v.P = 1;
+  for (int k = 0; k < n; ++k) v.P *= dims[k];
+  v.I = dims[n];
+  v.Q = 1;
+  for (int k = n + 1; k < N; ++k) v.Q *= dims[k];
+  return v;
+}
+
+int64_t numel(int N, const int64_t* dims) {
+  int64_t s = 1;
+  for (int k = 0; k < N; ++k) s *= dims[k];
+  return s;
+}
+
+bool valid_dims(int N, const int64_t* dims) {
+  if (!dims || N < 1 || N > TK_MAX_ORDER) return false;
+  double tot = 1.0;
+  for (int k = 0; k < N; ++k) {
+    if (dims[k] <= 0) return false;
+    tot *= (double)dims[k];
+  }
+  return tot < 9.0e18;
+}
+
+bool valid_ranks(int N, const int64_t* dims, const int32_t* ranks) {
+  if (!ranks) return false;
+  for (int n = 0; n < N; ++n) {
+    if (ranks[n] < 1 || ranks[n] > dims[n] || ranks[n] > 64) return false;
+    double others = 1.0;
+    for (int k = 0; k < N; ++k)
+      if (k != n) others *= ranks[k];
+    if (N > 1 && (double)ranks[n] > others) return false;
+  }
+  return true;
+}
+
+bool valid_dtype(int dt) { return dt == TK_F64 || dt == TK_F32 || dt == TK_BF16; }
+
+// ---------------------------------------------------------------------------
+// Device status block read back once per sweep.
+struct DevStatus {
+  int status;
+  int pad;
+  double res2;
+  double energy;
+  double norm2;
+  double rsum;
+};
+
+// Workspace of one mode solve on view v with rank R.
+struct ModeWs {
+  double *L, *Lnext, *Lacc, *CL, *Cq, *GV, *Q1;
+  void *Lq, *Lr;               // compute type
+  void *parts;                 // lacc/Y partials (compute type)
+  double *gparts, *sparts;     // Gram partials, scalar partials
+  void* V;                     // generic path: J x R (compute type)
+  DevStatus* st;
+};
+
+void carve_mode(Arena& ar, int xdt, const View& v, int R, ModeWs& w) {
+  const int cdt = cdtype(xdt);
+  const size_t cs = dsize(cdt);
+  const int64_t IR = v.I * (int64_t)R;
+  w.L = (double*)ar.take(IR * 8);
+  w.Lnext = (double*)ar.take(IR * 8);
+  w.Lacc = (double*)ar.take(IR * 8);
+  w.Q1 = (double*)ar.take(IR * 8);
+  w.CL = (double*)ar.take(64 * 64 * 8);
+  w.Cq = (double*)ar.take(64 * 64 * 8);
+  w.GV = (double*)ar.take(64 * 64 * 8);
+  w.Lq = ar.take(IR * cs);
+  w.Lr = ar.take(IR * cs);
+  w.parts = ar.take((size_t)NWG_MAX * IR * cs);
+  w.gparts = (double*)ar.take((size_t)NWG_MAX * R * R * 8);
+  w.sparts = (double*)ar.take((size_t)NWG_MAX * 8 * 2);
+  w.st = (DevStatus*)ar.take(sizeof(DevStatus));
+  if (!fused_supported(xdt, v, R, TK_RESID_EXPLICIT)) w.V = ar.take((size_t)v.J() * R * cs);
+  else w.V = nullptr;
+}
+
+struct Opts {
+  double tol;
+  int max_iters;
+  int resid_mode;
+  uint64_t seed;
+  const int32_t* order;
+};
+
+int read_opts(const tk_als_opts* o, int N, Opts& out) {
+  out.tol = 1e-4;
+  out.max_iters = 50;
+  out.resid_mode = TK_RESID_TRACE;
+  out.seed = 0;
+  out.order = nullptr;
+  if (!o) return TK_OK;
+  if (o->struct_size < sizeof(tk_als_opts)) return TK_ERR_INVALID_ARG;
+  if (!(o->tol >= 0.0) || o->max_iters < 0) return TK_ERR_INVALID_ARG;
+  if (o->resid_mode != TK_RESID_TRACE && o->resid_mode != TK_RESID_EXPLICIT)
+    return TK_ERR_INVALID_ARG;
+  out.tol = o->tol;
+  out.max_iters = o->max_iters;
+  out.resid_mode = o->resid_mode;
+  out.seed = o->seed;
+  out.order = o->order;
+  if (out.order) {
+    bool seen[TK_MAX_ORDER] = {false};
+    for (int k = 0; k < N; ++k) {
+      int m = out.order[k];
+      if (m < 0 || m >= N || seen[m]) return TK_ERR_INVALID_ARG;
+      seen[m] = true;
+    }
+  }
+  return TK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Small FP64 building blocks
+
+// Reduced QR (CholeskyQR2) of the FP64 m x r matrix L into Q (FP64).
+void qr_enqueue(const double* L, int64_t m, int r, double* Q, double* Q1, double* C1,
+                double* C2, int* status, hipStream_t s) {
+  launch_gram<double>(L, m, r, C1, s);
+  launch_chol(C1, r, status, s);
+  launch_row_solve<double>(L, m, r, C1, 0, Q1, nullptr, s);
+  launch_gram<double>(Q1, m, r, C2, s);
+  launch_chol(C2, r, status, s);
+  launch_row_solve<double>(Q1, m, r, C2, 0, Q, nullptr, s);
+}
+
+int read_status(const DevStatus* d, DevStatus* h, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(h, d, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return TK_OK;
+}
+
+// ||X||^2 in FP64 (deterministic two-stage reduction).
+int norm2_enqueue(const void* X, int xdt, int64_t n, double* sparts, double* out,
+                  hipStream_t s) {
+  int chunks = (int)std::min<int64_t>(NWG_MAX, std::max<int64_t>(1, ceil_div(n, 65536)));
+  launch_norm2_parts(X, xdt, n, chunks, sparts, s);
+  launch_reduce_parts<double>(sparts, chunks, 1, 1, out, s);
+  return TK_OK;
+}
+
+struct ModeResult {
+  int iters, converged, sweeps;
+  double resid;
+};
+
+// Y (FP64, I x R) = B_(n) S  (Section 5 initial sketch), partial-reduced.
+void init_enqueue(const void* X, int xdt, const View& v, int R, uint64_t seed, int mode,
+                  ModeWs& w, double* Yout, hipStream_t s) {
+  const int64_t IR = v.I * (int64_t)R;
+  if (fused_supported(xdt, v, R, TK_RESID_TRACE)) {
+    FusedArgs f{};
+    f.X = X; f.x_dtype = xdt; f.v = v; f.R = R;
+    f.lacc_parts = (float*)w.parts;
+    f.sketch = 1; f.seed = seed; f.mode = mode;
+    int nwg = launch_fused(f, NWG_MAX, s);
+    launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Yout, s);
+  } else {
+    LpassArgs a{};
+    a.X = X; a.x_dtype = xdt; a.v = v; a.v_kind = 1; a.R = R; a.seed = seed; a.mode = mode;
+    a.parts = w.parts;
+    int chunks = lpass_chunks(v, R, NWG_MAX);
+    launch_lpass(a, chunks, s);
+    if (cdtype(xdt) == TK_F64)
+      launch_reduce_parts<double>((const double*)w.parts, chunks, IR, IR, Yout, s);
+    else
+      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, Yout, s);
+  }
+}
+
+// One sweep of Algorithm 3.3 from w.L: R-update (never stored when fused),
+// L-update into w.Lnext, residual into st->res2.
+void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
+                   int resid_mode, ModeWs& w, hipStream_t s) {
+  const int64_t IR = v.I * (int64_t)R;
+  const int cdt = cdtype(xdt);
+  // prep: L~ = L (L^T L)^{-1}, quantised; Gram of the quantised L~ (FP64).
+  launch_gram<double>(w.L, v.I, R, w.CL, s);
+  launch_chol(w.CL, R, &w.st->status, s);
+  if (cdt == TK_F64) {
+    launch_row_solve<double>(w.L, v.I, R, w.CL, 1, (double*)w.Lq, nullptr, s);
+    launch_gram<double>((const double*)w.Lq, v.I, R, w.Cq, s);
+  } else {
+    launch_row_solve<float>(w.L, v.I, R, w.CL, 1, (float*)w.Lq, nullptr, s);
+    launch_gram<float>((const float*)w.Lq, v.I, R, w.Cq, s);
+  }
+  launch_chol(w.Cq, R, &w.st->status, s);
+  const bool expl = resid_mode == TK_RESID_EXPLICIT;
+  if (expl) {
+    if (cdt == TK_F64) launch_convert<double>(w.L, IR, (double*)w.Lr, s);
+    else launch_convert<float>(w.L, IR, (float*)w.Lr, s);
+  }
+  int nres = 0;
+  if (fused_supported(xdt, v, R, resid_mode)) {
+    FusedArgs f{};
+    f.X = X; f.x_dtype = xdt; f.v = v; f.R = R;
+    f.Lq = (const float*)w.Lq;
+    f.Lr = expl ? (const float*)w.Lr : nullptr;
+    f.lacc_parts = (float*)w.parts;
+    f.gv_parts = w.gparts;
+    f.resid_parts = w.sparts;
+    int nwg = launch_fused(f, NWG_MAX, s);
+    launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, w.Lacc, s);
+    launch_reduce_parts<double>(w.gparts, 4 * nwg, (int64_t)R * R, (int64_t)R * R, w.GV, s);
+    nres = 4 * nwg;
+  } else {
+    VpassArgs a{};
+    a.X = X; a.x_dtype = xdt; a.v = v;
+    a.W = w.Lq; a.w_ldi = R; a.w_ldo = 1; a.O = R;
+    a.out = w.V; a.out_kind = 0;
+    a.Lr = expl ? w.Lr : nullptr;
+    a.resid_parts = expl ? w.sparts : nullptr;
+    launch_vpass(a, NWG_MAX, &nres, s);
+    int gch = (int)std::min<int64_t>(NWG_MAX, std::max<int64_t>(1, ceil_div(v.J(), 4096)));
+    launch_gram_parts(w.V, cdt, v.J(), R, gch, w.gparts, s);
+    launch_reduce_parts<double>(w.gparts, gch, (int64_t)R * R, (int64_t)R * R, w.GV, s);
+    LpassArgs l{};
+    l.X = X; l.x_dtype = xdt; l.v = v; l.v_kind = 0; l.V = w.V; l.R = R;
+    l.parts = w.parts;
+    int chunks = lpass_chunks(v, R, NWG_MAX);
+    launch_lpass(l, chunks, s);
+    if (cdt == TK_F64)
+      launch_reduce_parts<double>((const double*)w.parts, chunks, IR, IR, w.Lacc, s);
+    else
+      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, w.Lacc, s);
+  }
+  double* rsum = nullptr;
+  if (expl) {
+    launch_reduce_parts<double>(w.sparts, nres, 1, 1, &w.st->rsum, s);
+    rsum = &w.st->rsum;
+  }
+  // finish: L_{k+1} = L_acc G_V^{-1}; res^2 from the Grams (or explicit).
+  launch_chol(w.GV, R, &w.st->status, s);
+  launch_row_solve<double>(w.Lacc, v.I, R, w.GV, 1, w.Lnext, nullptr, s);
+  launch_trace_resid(w.Cq, w.GV, R, norm2, rsum, &w.st->res2, s);
+}
+
+// Algorithm 3.3 on the mode view of X with rank R, initial guess of
+// Section 5, stop test E5.01 (first at k = 1, against norm_a = ||A||_F of the
+// input tensor); normb2 = ||X||_F^2 of the tensor being swept (trace form of
+// the residual).  On return U64 (FP64 I x R) holds Q of the reduced QR of
+// the returned L.
+int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, double normb2,
+               double norm_a, int mode, ModeWs& w, double* U64, ModeResult& mr,
+               hipStream_t s) {
+  mr.iters = 0; mr.converged = 1; mr.sweeps = 0; mr.resid = 0.0;
+  if (R == v.I) {
+    launch_identity<double>(U64, v.I, s);
+    return TK_OK;
+  }
+  DevStatus h{};
+  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
+  init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, s);
+  qr_enqueue(w.Lacc, v.I, R, w.L, w.Q1, w.CL, w.Cq, &w.st->status, s);
+  int rc = read_status(w.st, &h, s);
+  if (rc) return rc;
+  if (h.status) return h.status;
+  const double nA = norm_a;
+  double res_prev = 0.0;
+  for (int k = 0;; ++k) {
+    sweep_enqueue(X, xdt, v, R, normb2, o.resid_mode, w, s);
+    mr.sweeps++;
+    rc = read_status(w.st, &h, s);
+    if (rc) return rc;
+    if (h.status) return h.status;
+    double res = sqrt(h.res2 > 0.0 ? h.res2 : 0.0);
+    if (!isfinite(res)) return TK_ERR_NONFINITE;
+    mr.resid = res;
+    mr.iters = k;
+    if (k >= 1 && fabs(res_prev - res) <= o.tol * nA) { mr.converged = 1; break; }
+    if (k >= o.max_iters) { mr.converged = 0; break; }
+    std::swap(w.L, w.Lnext);
+    res_prev = res;
+  }
+  qr_enqueue(w.L, v.I, R, U64, w.Q1, w.CL, w.Cq, &w.st->status, s);
+  rc = read_status(w.st, &h, s);
+  if (rc) return rc;
+  return h.status;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace plan of the drivers.
+
+size_t max_mode_ws(int xdt, int N, const int64_t* dims_in, const int32_t* ranks, bool st,
+                   const int32_t* order) {
+  // measure every mode solve at the shape it runs on
+  int64_t dims[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) dims[k] = dims_in[k];
+  size_t mx = 0;
+  for (int t = 0; t < N; ++t) {
+    int n = order ? order[t] : t;
+    View v = mode_view(N, dims, n);
+    Arena ar(nullptr, (size_t)-1);
+    ModeWs w;
+    carve_mode(ar, st ? cdtype(xdt) == TK_F64 ? xdt : (t == 0 ? xdt : TK_F32) : xdt, v,
+               ranks[n], w);
+    mx = std::max(mx, ar.off);
+    if (st) dims[n] = ranks[n];
+  }
+  return mx;
+}
+
+// Bytes of the ping-pong buffers holding intermediate tensors of a TTM chain.
+void chain_sizes(int N, const int64_t* dims_in, const int32_t* ranks, const int32_t* order,
+                 int64_t* maxa, int64_t* maxb) {
+  int64_t dims[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) dims[k] = dims_in[k];
+  *maxa = 1; *maxb = 1;
+  for (int t = 0; t < N - 1; ++t) {
+    int n = order ? order[t] : t;
+    dims[n] = ranks[n];
+    int64_t e = numel(N, dims);
+    if (t % 2 == 0) *maxa = std::max(*maxa, e);
+    else *maxb = std::max(*maxb, e);
+  }
+}
+
+size_t driver_ws(int which, int xdt, int N, const int64_t* dims, const int32_t* ranks,
+                 const int32_t* order) {
+  size_t mw = max_mode_ws(xdt, N, dims, ranks, which == 1, order);
+  int64_t ea, eb;
+  chain_sizes(N, dims, ranks, order, &ea, &eb);
+  const size_t cs = dsize(cdtype(xdt));
+  size_t u64 = 0;
+  for (int n = 0; n < N; ++n) u64 += align_up((size_t)dims[n] * ranks[n] * 8);
+  return align_up(mw) + align_up(ea * cs) + align_up(eb * cs) + u64 + 4096;
+}
+
+int ttm_enqueue(const void* X, int xdt, int N, const int64_t* dims, int mode, const void* M,
+                int64_t J, int trans, void* Y, hipStream_t s) {
+  View v = mode_view(N, dims, mode);
+  VpassArgs a{};
+  a.X = X; a.x_dtype = xdt; a.v = v;
+  a.W = M;
+  if (trans) { a.w_ldi = J; a.w_ldo = 1; }
+  else { a.w_ldi = 1; a.w_ldo = v.I; }
+  a.O = J; a.out = Y; a.out_kind = 1;
+  int used = 0;
+  return launch_vpass(a, NWG_MAX, &used, s);
+}
+
+int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* dims,
+               const int32_t* ranks, const tk_als_opts* opts, void* const* U, void* G,
+               void* ws, size_t ws_bytes, tk_als_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (!valid_dtype(adt)) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A || !U || !G || !valid_dims(N, dims) || !valid_ranks(N, dims, ranks))
+    return TK_ERR_INVALID_ARG;
+  for (int n = 0; n < N; ++n)
+    if (!U[n]) return TK_ERR_INVALID_ARG;
+  Opts o;
+  int rc = read_opts(opts, N, o);
+  if (rc) return rc;
+  const int32_t* order = which == 1 ? o.order : nullptr;
+  size_t need = driver_ws(which, adt, N, dims, ranks, order);
+  if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
+
+  hipStream_t s = (hipStream_t)stream;
+  const int cdt = cdtype(adt);
+  const size_t cs = dsize(cdt);
+  int64_t ea, eb;
+  chain_sizes(N, dims, ranks, order, &ea, &eb);
+  Arena ar(ws, ws_bytes);
+  void* bufA = ar.take(ea * cs);
+  void* bufB = ar.take(eb * cs);
+  double* U64[TK_MAX_ORDER];
+  for (int n = 0; n < N; ++n) U64[n] = (double*)ar.take((size_t)dims[n] * ranks[n] * 8);
+  Arena mar(ar.base + ar.off, ar.cap - ar.off);
+
+  // ||A||^2 once (E5.01 uses the input's norm for every mode).
+  ModeWs w0;
+  {
+    Arena tmp = mar;
+    carve_mode(tmp, adt, mode_view(N, dims, 0), ranks[0], w0);
+  }
+  HIPCHK(hipMemsetAsync(w0.st, 0, sizeof(DevStatus), s));
+  norm2_enqueue(A, adt, numel(N, dims), w0.sparts, &w0.st->norm2, s);
+  DevStatus h{};
+  rc = read_status(w0.st, &h, s);
+  if (rc) return rc;
+  const double norm2 = h.norm2;
+  if (!isfinite(norm2)) return TK_ERR_NONFINITE;
+  if (info) info->norm_a = sqrt(norm2);
+
+  int worst = TK_OK;
+  double normb2 = norm2;
+  int64_t cur[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) cur[k] = dims[k];
+  const void* B = A;
+  int bdt = adt;
+  for (int t = 0; t < N; ++t) {
+    const int n = order ? order[t] : t;
+    View v = mode_view(N, which == 1 ? cur : dims, n);
+    const int R = ranks[n];
+    Arena tmp = mar;
+    ModeWs w;
+    carve_mode(tmp, which == 1 ? bdt : adt, v, R, w);
+    ModeResult mr;
+    if (which == 1 && t > 0) {
+      // ||B||^2 of the truncated tensor for the trace form of the residual
+      HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
+      norm2_enqueue(B, bdt, numel(N, cur), w.sparts, &w.st->norm2, s);
+      rc = read_status(w.st, &h, s);
+      if (rc) return rc;
+      normb2 = h.norm2;
+    }
+    rc = mode_solve(which == 1 ? B : A, which == 1 ? bdt : adt, v, R, o, normb2, sqrt(norm2),
+                    n, w, U64[n], mr, s);
+    if (info) {
+      info->iters[n] = mr.iters;
+      info->converged[n] = mr.converged;
+      info->resid[n] = mr.resid;
+      info->sweeps += mr.sweeps;
+    }
+    if (rc < 0) {
+      if (info) info->status = rc;
+      return rc;
+    }
+    if (!mr.converged) worst = TK_NOT_CONVERGED;
+    // factor in the caller's dtype
+    const int64_t IR = v.I * (int64_t)R;
+    if (cdt == TK_F64) launch_convert<double>(U64[n], IR, (double*)U[n], s);
+    else launch_convert<float>(U64[n], IR, (float*)U[n], s);
+    if (which == 1) {
+      // B <- B x_n U_n^T (equals Algorithm 3.5's R_hat R^T)
+      void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
+      rc = ttm_enqueue(B, bdt, N, cur, n, U[n], R, 1, dst, s);
+      if (rc) return rc;
+      cur[n] = R;
+      B = dst;
+      bdt = cdt;
+    }
+  }
+  if (which == 0) {
+    // G = A x_1 U_1^T ... x_N U_N^T (Algorithm 3.4 last line)
+    for (int t = 0; t < N; ++t) {
+      void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
+      rc = ttm_enqueue(B, bdt, N, cur, t, U[t], ranks[t], 1, dst, s);
+      if (rc) return rc;
+      cur[t] = ranks[t];
+      B = dst;
+      bdt = cdt;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  if (info) info->status = worst;
+  return worst;
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+const char* tk_status_string(int32_t st) {
+  switch (st) {
+    case TK_OK: return "TK_OK";
+    case TK_NOT_CONVERGED: return "TK_NOT_CONVERGED";
+    case TK_ERR_INVALID_ARG: return "TK_ERR_INVALID_ARG";
+    case TK_ERR_UNSUPPORTED_DTYPE: return "TK_ERR_UNSUPPORTED_DTYPE";
+    case TK_ERR_WORKSPACE_TOO_SMALL: return "TK_ERR_WORKSPACE_TOO_SMALL";
+    case TK_ERR_RANK_DEFICIENT: return "TK_ERR_RANK_DEFICIENT";
+    case TK_ERR_NONFINITE: return "TK_ERR_NONFINITE";
+    case TK_ERR_HIP: return "TK_ERR_HIP";
+  }
+  return "TK_UNKNOWN_STATUS";
+}
+
+size_t als_workspace_bytes(int32_t which, int32_t a_dtype, int32_t N, const int64_t* dims,
+                           const int32_t* ranks) {
+  if ((which != 0 && which != 1) || !valid_dtype(a_dtype) || !valid_dims(N, dims) ||
+      !valid_ranks(N, dims, ranks))
+    return 0;
+  return driver_ws(which, a_dtype, N, dims, ranks, nullptr);
+}
+
+int als_sthosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                const int32_t* ranks, const tk_als_opts* opts, void* const* U, void* G,
+                void* ws, size_t ws_bytes, tk_als_info* info, void* stream) {
+  return run_driver(1, A, a_dtype, N, dims, ranks, opts, U, G, ws, ws_bytes, info, stream);
+}
+
+int als_thosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+               const int32_t* ranks, const tk_als_opts* opts, void* const* U, void* G,
+               void* ws, size_t ws_bytes, tk_als_info* info, void* stream) {
+  return run_driver(0, A, a_dtype, N, dims, ranks, opts, U, G, ws, ws_bytes, info, stream);
+}
+
+int ttm(const void* X, int32_t x_dtype, int32_t N, const int64_t* dims, int32_t mode,
+        const void* M, int32_t m_dtype, int64_t J, int32_t trans_m, void* Y, int32_t y_dtype,
+        void* stream) {
+  if (!valid_dtype(x_dtype) || !valid_dtype(m_dtype) || !valid_dtype(y_dtype))
+    return TK_ERR_UNSUPPORTED_DTYPE;
+  if (m_dtype != cdtype(x_dtype) || y_dtype != cdtype(x_dtype)) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!X || !M || !Y || !valid_dims(N, dims) || mode < 0 || mode >= N || J < 1 ||
+      (trans_m != 0 && trans_m != 1))
+    return TK_ERR_INVALID_ARG;
+  int rc = ttm_enqueue(X, x_dtype, N, dims, mode, M, J, trans_m, Y, (hipStream_t)stream);
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_ERR_HIP;
+}
+
+size_t tucker_reconstruct_workspace_bytes(int32_t dtype, int32_t N, const int32_t* ranks,
+                                          const int64_t* dims) {
+  if ((dtype != TK_F64 && dtype != TK_F32) || !valid_dims(N, dims) || !ranks) return 0;
+  int64_t cur[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) {
+    if (ranks[k] < 1) return 0;
+    cur[k] = ranks[k];
+  }
+  int64_t ea = 1, eb = 1;
+  for (int t = 0; t < N - 1; ++t) {
+    cur[t] = dims[t];
+    int64_t e = numel(N, cur);
+    if (t % 2 == 0) ea = std::max(ea, e);
+    else eb = std::max(eb, e);
+  }
+  return align_up(ea * dsize(dtype)) + align_up(eb * dsize(dtype)) + 256;
+}
+
+int tucker_reconstruct(const void* G, int32_t dtype, int32_t N, const int32_t* ranks,
+                       const int64_t* dims, const void* const* U, void* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (dtype != TK_F64 && dtype != TK_F32) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!G || !U || !out || !valid_dims(N, dims) || !ranks) return TK_ERR_INVALID_ARG;
+  for (int n = 0; n < N; ++n)
+    if (!U[n] || ranks[n] < 1) return TK_ERR_INVALID_ARG;
+  size_t need = tucker_reconstruct_workspace_bytes(dtype, N, ranks, dims);
+  if (N > 1 && (!ws || ws_bytes < need)) return TK_ERR_WORKSPACE_TOO_SMALL;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t cur[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) cur[k] = ranks[k];
+  int64_t ea = 1;
+  {
+    int64_t c2[TK_MAX_ORDER];
+    for (int k = 0; k < N; ++k) c2[k] = ranks[k];
+    for (int t = 0; t < N - 1; t += 2) {
+      c2[t] = dims[t];
+      ea = std::max(ea, numel(N, c2));
+      if (t + 1 < N) c2[t + 1] = dims[t + 1];
+    }
+  }
+  Arena ar(ws, ws_bytes);
+  int64_t eA = 1, eB = 1;
+  {
+    int64_t c3[TK_MAX_ORDER];
+    for (int k = 0; k < N; ++k) c3[k] = ranks[k];
+    for (int t = 0; t < N - 1; ++t) {
+      c3[t] = dims[t];
+      if (t % 2 == 0) eA = std::max(eA, numel(N, c3));
+      else eB = std::max(eB, numel(N, c3));
+    }
+  }
+  void* bufA = ar.take(eA * dsize(dtype));
+  void* bufB = ar.take(eB * dsize(dtype));
+  const void* X = G;
+  for (int t = 0; t < N; ++t) {
+    void* dst = (t == N - 1) ? out : ((t % 2 == 0) ? bufA : bufB);
+    int rc = ttm_enqueue(X, dtype, N, cur, t, U[t], dims[t], 0, dst, s);
+    if (rc) return rc;
+    cur[t] = dims[t];
+    X = dst;
+  }
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_ERR_HIP;
+}
+
+size_t contract_allbut_workspace_bytes(int32_t dtype, int32_t N, const int64_t* xdims,
+                                       int32_t mode, int64_t J) {
+  if ((dtype != TK_F64 && dtype != TK_F32) || !valid_dims(N, xdims) || mode < 0 ||
+      mode >= N || J < 1 || J > 64)
+    return 0;
+  View v = mode_view(N, xdims, mode);
+  int chunks = lpass_chunks(v, J, NWG_MAX);
+  return align_up((size_t)chunks * v.I * J * dsize(dtype)) + align_up(v.I * J * 8) + 256;
+}
+
+int contract_allbut(const void* X, const void* Y, int32_t dtype, int32_t N,
+                    const int64_t* xdims, int32_t mode, int64_t J, void* K, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (dtype != TK_F64 && dtype != TK_F32) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!X || !Y || !K || !valid_dims(N, xdims) || mode < 0 || mode >= N || J < 1 || J > 64)
+    return TK_ERR_INVALID_ARG;
+  size_t need = contract_allbut_workspace_bytes(dtype, N, xdims, mode, J);
+  if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
+  hipStream_t s = (hipStream_t)stream;
+  View v = mode_view(N, xdims, mode);
+  int chunks = lpass_chunks(v, J, NWG_MAX);
+  Arena ar(ws, ws_bytes);
+  void* parts = ar.take((size_t)chunks * v.I * J * dsize(dtype));
+  double* red = (double*)ar.take(v.I * J * 8);
+  LpassArgs a{};
+  a.X = X; a.x_dtype = dtype; a.v = v; a.v_kind = 2; a.V = Y; a.R = J; a.parts = parts;
+  launch_lpass(a, chunks, s);
+  const int64_t n = v.I * J;
+  if (dtype == TK_F64) {
+    launch_reduce_parts<double>((const double*)parts, chunks, n, n, red, s);
+    launch_convert<double>(red, n, (double*)K, s);
+  } else {
+    launch_reduce_parts<float>((const float*)parts, chunks, n, n, red, s);
+    launch_convert<float>(red, n, (float*)K, s);
+  }
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_ERR_HIP;
+}
+
+int als_init_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims, int32_t mode,
+                  int32_t R, uint64_t seed, void* Y, void* L0, double* norm2, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!valid_dtype(a_dtype)) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A || !Y || !L0 || !norm2 || !valid_dims(N, dims) || mode < 0 || mode >= N || R < 1 ||
+      R > 64 || R > dims[mode])
+    return TK_ERR_INVALID_ARG;
+  View v = mode_view(N, dims, mode);
+  Arena meas(nullptr, (size_t)-1);
+  ModeWs w;
+  carve_mode(meas, a_dtype, v, R, w);
+  if (!ws || ws_bytes < meas.off) return TK_ERR_WORKSPACE_TOO_SMALL;
+  Arena ar(ws, ws_bytes);
+  carve_mode(ar, a_dtype, v, R, w);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
+  norm2_enqueue(A, a_dtype, numel(N, dims), w.sparts, &w.st->norm2, s);
+  init_enqueue(A, a_dtype, v, R, seed, mode, w, (double*)Y, s);
+  qr_enqueue((const double*)Y, v.I, R, (double*)L0, w.Q1, w.CL, w.Cq, &w.st->status, s);
+  DevStatus h{};
+  int rc = read_status(w.st, &h, s);
+  if (rc) return rc;
+  *norm2 = h.norm2;
+  return h.status;
+}
+
+int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                   int32_t mode, int32_t R, const void* L, void* L_next, double norm2,
+                   int32_t resid_mode, double* res2, void* ws, size_t ws_bytes,
+                   void* stream) {
+  if (!valid_dtype(a_dtype)) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A || !L || !L_next || !res2 || !valid_dims(N, dims) || mode < 0 || mode >= N ||
+      R < 1 || R > 64 || R > dims[mode] ||
+      (resid_mode != TK_RESID_TRACE && resid_mode != TK_RESID_EXPLICIT))
+    return TK_ERR_INVALID_ARG;
+  View v = mode_view(N, dims, mode);
+  Arena meas(nullptr, (size_t)-1);
+  ModeWs w;
+  carve_mode(meas, a_dtype, v, R, w);
+  if (!ws || ws_bytes < meas.off) return TK_ERR_WORKSPACE_TOO_SMALL;
+  Arena ar(ws, ws_bytes);
+  carve_mode(ar, a_dtype, v, R, w);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
+  HIPCHK(hipMemcpyAsync(w.L, L, v.I * (size_t)R * 8, hipMemcpyDeviceToDevice, s));
+  sweep_enqueue(A, a_dtype, v, R, norm2, resid_mode, w, s);
+  HIPCHK(hipMemcpyAsync(L_next, w.Lnext, v.I * (size_t)R * 8, hipMemcpyDeviceToDevice, s));
+  DevStatus h{};
+  int rc = read_status(w.st, &h, s);
+  if (rc) return rc;
+  *res2 = h.res2;
+  return h.status;
+}
+
+int qr_f64(const void* L, int64_t m, int32_t r, void* Q, void* Rhat, void* ws, size_t ws_bytes,
+           void* stream) {
+  (void)Rhat;
+  if (!L || !Q || m < 1 || r < 1 || r > 64 || r > m) return TK_ERR_INVALID_ARG;
+  size_t need = align_up(m * (size_t)r * 8) + 2 * align_up(64 * 64 * 8) + align_up(64);
+  if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
+  Arena ar(ws, ws_bytes);
+  double* Q1 = (double*)ar.take(m * (size_t)r * 8);
+  double* C1 = (double*)ar.take(64 * 64 * 8);
+  double* C2 = (double*)ar.take(64 * 64 * 8);
+  DevStatus* st = (DevStatus*)ar.take(sizeof(DevStatus));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(st, 0, sizeof(DevStatus), s));
+  qr_enqueue((const double*)L, m, r, (double*)Q, Q1, C1, C2, &st->status, s);
+  DevStatus h{};
+  int rc = read_status(st, &h, s);
+  if (rc) return rc;
+  return h.status;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t als_sthosvd_batched_workspace_bytes(int32_t count, const int64_t* dims3,
+                                           const int32_t* ranks3) {
+  if (count < 1 || !dims3 || !ranks3) return 0;
+  size_t mx = 0;
+  for (int t = 0; t < count; ++t) {
+    if (!valid_dims(3, dims3 + 3 * t) || !valid_ranks(3, dims3 + 3 * t, ranks3 + 3 * t))
+      return 0;
+    mx = std::max(mx, driver_ws(1, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t, nullptr));
+  }
+  return mx;
+}
+
+int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t count,
+                        const int64_t* dims3, const int32_t* ranks3, const int64_t* a_off,
+                        const tk_als_opts* opts, void* U_packed, const int64_t* u_off,
+                        void* G_packed, const int64_t* g_off, int32_t* iters, int32_t* status,
+                        void* ws, size_t ws_bytes, void* stream) {
+  if (a_dtype != TK_F32) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A_packed || count < 1 || !dims3 || !ranks3 || !a_off || !U_packed || !u_off ||
+      !G_packed || !g_off)
+    return TK_ERR_INVALID_ARG;
+  size_t need = als_sthosvd_batched_workspace_bytes(count, dims3, ranks3);
+  if (need == 0) return TK_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
+  Opts o;
+  int rc = read_opts(opts, 3, o);
+  if (rc) return rc;
+  int worst = TK_OK;
+  for (int t = 0; t < count; ++t) {
+    const float* A = (const float*)A_packed + a_off[t];
+    void* U[3];
+    for (int n = 0; n < 3; ++n) U[n] = (float*)U_packed + u_off[3 * t + n];
+    void* G = (float*)G_packed + g_off[t];
+    tk_als_info info;
+    tk_als_opts o2;
+    memset(&o2, 0, sizeof(o2));
+    o2.struct_size = sizeof(o2);
+    o2.tol = o.tol; o2.max_iters = o.max_iters; o2.resid_mode = o.resid_mode; o2.seed = o.seed;
+    rc = run_driver(1, A, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t, &o2, U, G, ws, ws_bytes,
+                    &info, stream);
+    if (status) status[t] = rc;
+    if (iters)
+      for (int n = 0; n < 3; ++n) iters[3 * t + n] = info.iters[n];
+    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+    else if (rc > 0 && worst == TK_OK) worst = rc;
+  }
+  return worst;
+}
+
+}  // extern "C"
+
+extern "C" int als_sweep_kernel(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                                int32_t mode, int32_t R, const float* Lq, double* Lacc,
+                                double* GV, int32_t reduce, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (a_dtype != TK_F32 && a_dtype != TK_BF16) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A || !Lq || !valid_dims(N, dims) || mode < 0 || mode >= N || R < 1 || R > 64 ||
+      R > dims[mode] || (reduce && (!Lacc || !GV)))
+    return TK_ERR_INVALID_ARG;
+  View v = mode_view(N, dims, mode);
+  Arena meas(nullptr, (size_t)-1);
+  ModeWs w;
+  carve_mode(meas, a_dtype, v, R, w);
+  if (!ws || ws_bytes < meas.off) return TK_ERR_WORKSPACE_TOO_SMALL;
+  Arena ar(ws, ws_bytes);
+  carve_mode(ar, a_dtype, v, R, w);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t IR = v.I * (int64_t)R;
+  if (fused_supported(a_dtype, v, R, TK_RESID_TRACE)) {
+    FusedArgs f{};
+    f.X = A; f.x_dtype = a_dtype; f.v = v; f.R = R;
+    f.Lq = Lq;
+    f.lacc_parts = (float*)w.parts;
+    f.gv_parts = w.gparts;
+    int nwg = launch_fused(f, NWG_MAX, s);
+    if (reduce) {
+      launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Lacc, s);
+      launch_reduce_parts<double>(w.gparts, 4 * nwg, (int64_t)R * R, (int64_t)R * R, GV, s);
+    }
+  } else {
+    VpassArgs a{};
+    a.X = A; a.x_dtype = a_dtype; a.v = v;
+    a.W = Lq; a.w_ldi = R; a.w_ldo = 1; a.O = R;
+    a.out = w.V; a.out_kind = 0;
+    int nres = 0;
+    launch_vpass(a, NWG_MAX, &nres, s);
+    int gch = (int)std::min<int64_t>(NWG_MAX, std::max<int64_t>(1, ceil_div(v.J(), 4096)));
+    launch_gram_parts(w.V, TK_F32, v.J(), R, gch, w.gparts, s);
+    LpassArgs l{};
+    l.X = A; l.x_dtype = a_dtype; l.v = v; l.v_kind = 0; l.V = w.V; l.R = R;
+    l.parts = w.parts;
+    int chunks = lpass_chunks(v, R, NWG_MAX);
+    launch_lpass(l, chunks, s);
+    if (reduce) {
+      launch_reduce_parts<double>(w.gparts, gch, (int64_t)R * R, (int64_t)R * R, GV, s);
+      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, Lacc, s);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_ERR_HIP;
+}

@@ -1,0 +1,101 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tk_device.h"
+#include "../../include/tucker_als.h"
+
+namespace tk {
+
+// A Gram is declared singular when a squared Cholesky pivot drops to
+// PIVOT_TOL times its largest diagonal entry (Remark 3).
+constexpr double PIVOT_TOL = 1e-13;
+
+template <typename T> struct Store;
+template <> struct Store<double> {
+  __host__ __device__ static double cvt(double x) { return x; }
+};
+template <> struct Store<float> {
+  __host__ __device__ static float cvt(double x) { return (float)x; }
+};
+template <> struct Store<bf16_t> {
+  __host__ __device__ static bf16_t cvt(double x) { return f32_to_bf16((float)x); }
+};
+
+// ---------------------------------------------------------------- small LA
+template <typename T>
+void launch_gram(const T* X, int64_t m, int r, double* G, hipStream_t s);
+void launch_chol(double* G, int r, int* status, hipStream_t s);
+template <typename TO>
+void launch_row_solve(const double* B, int64_t m, int r, const double* C, int gram,
+                      TO* X, double* Xd, hipStream_t s);
+void launch_trace_resid(const double* Cq, const double* D, int r, double norm2,
+                        const double* explicit_sum, double* out, hipStream_t s);
+template <typename T>
+void launch_reduce_parts(const T* in, int parts, int64_t n, int64_t stride, double* out,
+                         hipStream_t s);
+template <typename T>
+void launch_identity(T* U, int64_t n, hipStream_t s);
+template <typename T>
+void launch_convert(const double* in, int64_t n, T* out, hipStream_t s);
+
+// ---------------------------------------------------------------- streaming
+// Contraction over the mode index (generic VALU path):
+//   out(j, o) = sum_i W(i, o) X[p, i, q],  j = p*Q + q,  0 <= o < O
+// W(i, o) = W[i*w_ldi + o*w_ldo] (compute type C).
+// out_kind 0: row-major matrix out[j*O + o] (type C)
+// out_kind 1: tensor out[(p*O + o)*Q + q]   (type C)
+// resid (optional, FP64 per workgroup): sum_j ||x_j - Lr v_j||^2 where
+//   Lr(i, o) = Lr[i*O + o] (type C) and v_j = out(j, :).
+struct VpassArgs {
+  const void* X; int x_dtype; View v;
+  const void* W; int64_t w_ldi, w_ldo; int64_t O;
+  void* out; int out_kind;
+  const void* Lr; double* resid_parts;
+};
+int launch_vpass(const VpassArgs& a, int nwg_max, int* nwg_used, hipStream_t s);
+
+// Contraction over fibres (generic VALU path):
+//   L(i, r) = sum_j X[p, i, q] V(j, r)
+// v_kind 0: V(j, r) = V[j*R + r]                   (type C)
+// v_kind 1: V(j, r) = sketch(seed, mode, j*R + r)  (Section 5 initial guess)
+// v_kind 2: V(j, r) = Y[p, r, q]                   (tensor, x_dtype)
+// Per-workgroup partials parts[c*I*R + i*R + r] (type C) for fibre chunk c;
+// norm2_parts (optional) receives per-chunk sums of X^2 (FP64).
+struct LpassArgs {
+  const void* X; int x_dtype; View v;
+  int v_kind; const void* V; int64_t R; uint64_t seed; int mode;
+  void* parts; double* norm2_parts;
+};
+int lpass_chunks(const View& v, int64_t R, int nwg_max);
+void launch_lpass(const LpassArgs& a, int chunks, hipStream_t s);
+
+// G = V^T V partials over row chunks: parts[c*R*R + a*R + b] (FP64).
+void launch_gram_parts(const void* V, int c_dtype, int64_t J, int64_t R, int chunks,
+                       double* parts, hipStream_t s);
+
+// Sum of squares partials (FP64) over `chunks` workgroups.
+void launch_norm2_parts(const void* X, int x_dtype, int64_t n, int chunks, double* parts,
+                        hipStream_t s);
+
+// Fused ALS sweep on the matrix cores (FP32/BF16 storage, I <= 256, R <= 64):
+// one read of every fibre a_j gives v_j = Lq^T a_j, G_V += v_j v_j^T and
+// L_acc += a_j v_j^T (and, with resid, sum ||a_j - Lr v_j||^2).
+struct FusedArgs {
+  const void* X; int x_dtype; View v; int R;
+  const float* Lq;       // I x R, quantised L~ (compute type float)
+  const float* Lr;       // I x R, factor for the explicit residual (or null)
+  float* lacc_parts;     // [nwg][I][R]
+  double* gv_parts;      // [nwg][R][R]
+  double* resid_parts;   // [nwg] (only when Lr != null)
+  int sketch; uint64_t seed; int mode;  // init variant: V = sketch, no G_V
+  double* norm2_parts;   // [nwg] (init variant)
+};
+// Shapes the fused kernel takes (LDS budget), for the given residual mode.
+bool fused_supported(int x_dtype, const View& v, int R, int resid_mode);
+// Launches and returns the number of workgroups W; L_acc partials are
+// [W][I][R], Gram and residual partials [4W] (one per wave).
+int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
+
+}  // namespace tk

@@ -1,0 +1,160 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2004_02583_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tucker_als.h")
+
+FAKE = ctypes.c_void_p(0x100000)  # never dereferenced: validation comes first
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load_library()
+
+
+def header_symbols():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^TK_API\s+[\w\s\*]*?\b(\w+)\s*\(", src, re.M)))
+
+
+def test_header_symbols_exported(lib):
+    syms = header_symbols()
+    assert len(syms) >= 14
+    assert sorted(L.EXPORTS) == syms
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_status_strings(lib):
+    for code, name in L.STATUS.items():
+        assert lib.tk_status_string(code).decode() == name
+
+
+def _drv(lib, fn, adt=1, N=3, dims=(8, 9, 10), ranks=(2, 3, 4), opts=None, ws_bytes=1 << 30,
+         ws=FAKE, A=FAKE, U=None, G=FAKE):
+    U = U if U is not None else L.ptrarr([0x100000] * max(N, 1))
+    return fn(A, adt, N, L.i64arr(dims) if dims is not None else None,
+              L.i32arr(ranks) if ranks is not None else None,
+              ctypes.byref(opts) if opts is not None else None, U, G, ws, ws_bytes, None,
+              None)
+
+
+@pytest.mark.parametrize("name", ["als_sthosvd", "als_thosvd"])
+def test_driver_validation(lib, name):
+    fn = getattr(lib, name)
+    assert _drv(lib, fn, adt=7) == -2
+    assert _drv(lib, fn, A=None) == -1
+    assert _drv(lib, fn, G=None) == -1
+    assert _drv(lib, fn, U=L.ptrarr([0x100000, 0, 0x100000])) == -1
+    assert _drv(lib, fn, N=0, dims=(), ranks=()) == -1
+    assert _drv(lib, fn, N=9, dims=(2,) * 9, ranks=(1,) * 9) == -1
+    assert _drv(lib, fn, dims=(8, 0, 10)) == -1
+    assert _drv(lib, fn, ranks=(9, 3, 4)) == -1          # R_n > I_n
+    assert _drv(lib, fn, ranks=(0, 3, 4)) == -1
+    assert _drv(lib, fn, ranks=(2, 3, 7)) == -1          # R_3 > R_1 R_2
+    assert _drv(lib, fn, ranks=None) == -1
+    assert _drv(lib, fn, ws_bytes=16) == -3
+    assert _drv(lib, fn, ws=None) == -3
+    o = L.tk_als_opts()
+    o.struct_size = ctypes.sizeof(o)
+    o.tol = -1.0
+    assert _drv(lib, fn, opts=o) == -1
+    o.tol = 1e-4
+    o.max_iters = -3
+    assert _drv(lib, fn, opts=o) == -1
+    o.max_iters = 5
+    o.resid_mode = 4
+    assert _drv(lib, fn, opts=o) == -1
+    o.resid_mode = 0
+    o.struct_size = 8
+    assert _drv(lib, fn, opts=o) == -1
+
+
+def test_bad_order(lib):
+    o = L.tk_als_opts()
+    o.struct_size = ctypes.sizeof(o)
+    o.tol = 1e-4
+    o.max_iters = 5
+    for bad in ([0, 0, 1], [0, 1, 3], [-1, 0, 1]):
+        keep = L.i32arr(bad)
+        o.order = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+        assert _drv(lib, lib.als_sthosvd, opts=o) == -1
+
+
+def test_workspace_queries(lib):
+    d, r = L.i64arr([20, 30, 40]), L.i32arr([4, 5, 6])
+    a = lib.als_workspace_bytes(1, 1, 3, d, r)
+    b = lib.als_workspace_bytes(0, 1, 3, d, r)
+    assert a > 0 and b > 0
+    assert lib.als_workspace_bytes(2, 1, 3, d, r) == 0
+    assert lib.als_workspace_bytes(1, 9, 3, d, r) == 0
+    assert lib.als_workspace_bytes(1, 1, 3, d, L.i32arr([21, 5, 6])) == 0
+    # larger tensors need more workspace
+    assert lib.als_workspace_bytes(1, 1, 3, L.i64arr([40, 60, 80]), r) > a
+    assert lib.tucker_reconstruct_workspace_bytes(1, 3, r, d) > 0
+    assert lib.tucker_reconstruct_workspace_bytes(2, 3, r, d) == 0
+    assert lib.contract_allbut_workspace_bytes(1, 3, d, 1, 5) > 0
+    assert lib.contract_allbut_workspace_bytes(1, 3, d, 3, 5) == 0
+    assert lib.als_sthosvd_batched_workspace_bytes(
+        2, L.i64arr([20, 30, 40, 16, 17, 18]), L.i32arr([4, 5, 6, 2, 2, 3])) > 0
+    assert lib.als_sthosvd_batched_workspace_bytes(
+        1, L.i64arr([20, 30, 40]), L.i32arr([40, 5, 6])) == 0
+
+
+def test_ttm_validation(lib):
+    d = L.i64arr([4, 5, 6])
+    assert lib.ttm(FAKE, 1, 3, d, 1, FAKE, 0, 3, 0, FAKE, 1, None) == -2   # M dtype
+    assert lib.ttm(FAKE, 2, 3, d, 1, FAKE, 1, 3, 0, FAKE, 2, None) == -2   # bf16 out
+    assert lib.ttm(FAKE, 1, 3, d, 3, FAKE, 1, 3, 0, FAKE, 1, None) == -1   # mode
+    assert lib.ttm(FAKE, 1, 3, d, 1, FAKE, 1, 0, 0, FAKE, 1, None) == -1   # J
+    assert lib.ttm(FAKE, 1, 3, d, 1, FAKE, 1, 3, 2, FAKE, 1, None) == -1   # trans
+    assert lib.ttm(None, 1, 3, d, 1, FAKE, 1, 3, 0, FAKE, 1, None) == -1
+
+
+def test_reconstruct_contract_step_validation(lib):
+    d, r = L.i64arr([4, 5, 6]), L.i32arr([2, 2, 2])
+    U = L.ptrarr([0x100000] * 3)
+    assert lib.tucker_reconstruct(FAKE, 2, 3, r, d, U, FAKE, FAKE, 1 << 20, None) == -2
+    assert lib.tucker_reconstruct(FAKE, 1, 3, r, d, U, FAKE, FAKE, 4, None) == -3
+    assert lib.tucker_reconstruct(FAKE, 1, 3, r, d, L.ptrarr([0x100000, 0, 0x100000]),
+                                  FAKE, FAKE, 1 << 20, None) == -1
+    assert lib.contract_allbut(FAKE, FAKE, 1, 3, d, 0, 3, FAKE, FAKE, 4, None) == -3
+    assert lib.contract_allbut(FAKE, FAKE, 2, 3, d, 0, 3, FAKE, FAKE, 1 << 20, None) == -2
+    n2 = ctypes.c_double()
+    assert lib.als_init_step(FAKE, 1, 3, d, 0, 5, 0, FAKE, FAKE, ctypes.byref(n2), FAKE,
+                             1 << 30, None) == -1          # R > I_mode
+    assert lib.als_init_step(FAKE, 1, 3, d, 0, 2, 0, FAKE, FAKE, ctypes.byref(n2), FAKE,
+                             16, None) == -3
+    assert lib.als_sweep_step(FAKE, 1, 3, d, 1, 2, FAKE, FAKE, 1.0, 3, ctypes.byref(n2), FAKE,
+                              1 << 30, None) == -1         # resid mode
+    assert lib.qr_f64(FAKE, 3, 4, FAKE, None, FAKE, 1 << 20, None) == -1   # r > m
+    assert lib.qr_f64(FAKE, 30, 4, FAKE, None, FAKE, 16, None) == -3
+
+
+def test_batched_validation(lib):
+    d3, r3 = L.i64arr([8, 9, 10]), L.i32arr([2, 3, 4])
+    off = L.i64arr([0])
+    u_off = L.i64arr([0, 16, 43])
+    assert lib.als_sthosvd_batched(FAKE, 0, 1, d3, r3, off, None, FAKE, u_off, FAKE, off, None,
+                                   None, FAKE, 1 << 30, None) == -2
+    assert lib.als_sthosvd_batched(FAKE, 1, 0, d3, r3, off, None, FAKE, u_off, FAKE, off, None,
+                                   None, FAKE, 1 << 30, None) == -1
+    assert lib.als_sthosvd_batched(FAKE, 1, 1, d3, r3, off, None, FAKE, u_off, FAKE, off, None,
+                                   None, FAKE, 8, None) == -3
+
+
+def test_product_path_does_not_touch_oracle():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2004_02583_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in txt.replace("oracle-free", ""), f

@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Both sides receive the same seeded input: the oracle runs in FP64 on exactly
+the values the GPU holds (the FP32 or BF16 rounding of the FP64 master, or
+the FP64 master itself).  Tolerances:
+  * FP64 storage: 1e-10 relative on contractions, relerr within 1e-10;
+  * FP32 storage: contractions within a few FP32 roundings of an I-term sum
+    (rtol 2e-5 with an absolute floor scaled by the operands' norms),
+    relative reconstruction error within 1e-5 of the oracle's;
+  * BF16 storage: relerr (against the FP64 master) within 1e-2 of the
+    oracle's FP64 result.
+Subspaces are compared through principal angles (only span(U_n) is defined).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tucker_oracle as o
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+TDT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+def to_gpu(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(TDT[dt]).cuda().contiguous()
+
+
+def held(a, dt):
+    """FP64 copy of exactly the values the GPU holds."""
+    return to_gpu(a, dt).double().cpu().numpy()
+
+
+def np64(t):
+    return t.detach().double().cpu().numpy()
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------ TTM
+
+TTM_CASES = [
+    ((7, 9, 11), 1, 5, False),
+    ((7, 9, 11), 2, 13, True),      # Q == 1 (last mode), expansion
+    ((70, 3, 130), 0, 4, True),     # P == 1, ragged tiles
+    ((5, 200, 66), 1, 20, True),    # truncation 200 -> 20, ragged fibre tiles
+    ((3, 4, 5, 6), 3, 2, False),
+    ((65, 129), 0, 70, False),      # order 2, more outputs than one chunk
+]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dims,mode,J,trans", TTM_CASES)
+def test_ttm_parity(gpu_lib, dims, mode, J, trans, dt):
+    tk = gpu_lib
+    flush(f"ttm {dims} mode={mode} J={J} trans={trans} {dt}")
+    rng = np.random.default_rng(100 + mode)
+    X = rng.standard_normal(dims)
+    I = dims[mode]
+    M = rng.standard_normal((I, J) if trans else (J, I))
+    mdt = "f64" if dt == "f64" else "f32"
+    Y = tk.ttm(to_gpu(X, dt), to_gpu(M, mdt), mode, transpose=trans)
+    Mh = held(M, mdt)
+    want = o.ttm(held(X, dt), Mh.T if trans else Mh, mode)
+    got = np64(Y)
+    assert got.shape == want.shape
+    if dt == "f64":
+        np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+    else:
+        # FP32 accumulation of I products: error <~ I * 2^-24 * sum |x||m|
+        bound = I * 2.0 ** -24 * o.ttm(np.abs(held(X, dt)), np.abs(Mh.T if trans else Mh), mode)
+        assert np.all(np.abs(got - want) <= 4 * bound + 1e-30)
+
+
+def test_tucker_reconstruct_parity(gpu_lib):
+    tk = gpu_lib
+    rng = np.random.default_rng(5)
+    ranks, dims = (3, 5, 2, 4), (9, 7, 6, 70)
+    G = rng.standard_normal(ranks)
+    Us = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    for dt in ("f64", "f32"):
+        out = tk.tucker_reconstruct(to_gpu(G, dt), [to_gpu(u, dt) for u in Us])
+        want = o.tucker_to_tensor(held(G, dt), [held(u, dt) for u in Us])
+        tol = 1e-12 if dt == "f64" else 2e-5
+        assert np.max(np.abs(np64(out) - want)) <= tol * np.abs(want).max()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_contract_allbut_parity(gpu_lib, dt):
+    tk = gpu_lib
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((13, 70, 9))
+    for mode, J in ((0, 5), (1, 33), (2, 7)):
+        shp = list(X.shape)
+        shp[mode] = J
+        Y = rng.standard_normal(shp)
+        K = tk.contract_allbut(to_gpu(X, dt), to_gpu(Y, dt), mode)
+        want = o.unfold(held(X, dt), mode) @ o.unfold(held(Y, dt), mode).T
+        tol = 1e-11 if dt == "f64" else 3e-5
+        assert np.max(np.abs(np64(K) - want)) <= tol * np.abs(want).max()
+
+
+# --------------------------------------------------- single steps of ALS
+
+STEP_CASES = [((20, 30, 40), 0, 5), ((20, 30, 40), 1, 7), ((20, 30, 40), 2, 6),
+              ((100, 9, 70), 0, 20), ((12, 11, 10, 9), 2, 4)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("dims,mode,R", STEP_CASES)
+def test_init_step_parity(gpu_lib, dims, mode, R, dt):
+    tk = gpu_lib
+    flush(f"init {dims} mode={mode} R={R} {dt}")
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal(dims)
+    seed = 1234
+    Y, L0, n2 = tk.als_init_step(to_gpu(A, dt), mode, R, seed=seed)
+    Ah = held(A, dt)
+    An = o.unfold(Ah, mode)
+    S = o.init_sketch(seed, mode, An.shape[1], R)
+    want = An @ S
+    tol = 1e-12 if dt == "f64" else 1e-5
+    assert np.max(np.abs(np64(Y) - want)) <= tol * np.abs(want).max()
+    assert abs(n2 - o.frob(Ah) ** 2) <= 1e-12 * o.frob(Ah) ** 2
+    Q = np64(L0)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(R), atol=1e-12)
+    Qo, _ = o.qr_signfix(np64(Y))
+    np.testing.assert_allclose(Q, Qo, atol=1e-10)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("resid", ["trace", "explicit"])
+@pytest.mark.parametrize("dims,mode,R", STEP_CASES)
+def test_sweep_step_parity(gpu_lib, dims, mode, R, dt, resid):
+    """One fused sweep from a given L_k equals one literal iteration of
+    Algorithm 3.3: R_k = A^T L (L^T L)^{-1}, L_{k+1} = A R_k (R_k^T R_k)^{-1},
+    res_k = ||A - L_k R_k^T||."""
+    tk = gpu_lib
+    flush(f"sweep {dims} mode={mode} R={R} {dt} {resid}")
+    rng = np.random.default_rng(8)
+    A = synth.tucker_lowrank(rng, dims, tuple(min(R + 2, d) for d in dims), 0.05)[0]
+    Ah = held(A, dt)
+    An = o.unfold(Ah, mode)
+    Lk = rng.standard_normal((An.shape[0], R)) + 0.0
+    Lk, _ = np.linalg.qr(Lk)
+    Lk = Lk + 0.01 * rng.standard_normal(Lk.shape)
+    n2 = o.frob(Ah) ** 2
+    Ln, res2 = tk.als_sweep_step(to_gpu(Ah, dt), mode, torch.from_numpy(Lk).cuda(), n2,
+                                 resid_mode=resid)
+    Rk = o.als_r_update(An, Lk)
+    Lw = o.als_l_update(An, Rk)
+    rw = o.frob(An - Lk @ Rk.T)
+    got = np64(Ln)
+    tol = 1e-9 if dt == "f64" else 2e-4
+    assert np.max(np.abs(got - Lw)) <= tol * np.abs(Lw).max()
+    rg = np.sqrt(max(res2, 0.0))
+    rtol = 1e-9 if dt == "f64" else (1e-3 if resid == "explicit" else 5e-2)
+    assert abs(rg - rw) <= rtol * rw + 1e-6 * np.sqrt(n2) * (dt != "f64")
+
+
+def test_qr_parity(gpu_lib):
+    tk = gpu_lib
+    rng = np.random.default_rng(9)
+    for m, r in ((50, 7), (1024, 48), (64, 64)):
+        Lm = rng.standard_normal((m, r)) @ np.diag(np.logspace(0, 3, r))
+        Q = np64(tk.qr_f64(torch.from_numpy(Lm).cuda()))
+        Qo, _ = o.qr_signfix(Lm)
+        np.testing.assert_allclose(Q, Qo, atol=1e-9)
+        np.testing.assert_allclose(Q.T @ Q, np.eye(r), atol=1e-12)
+
+
+# ------------------------------------------------------- drivers
+
+def _relerr_of(A64, G, Us):
+    return o.relerr(A64, np64(G), [np64(u) for u in Us])
+
+
+def test_small_fp64_workload_parity(gpu_lib):
+    """64^3 FP64, ranks (8,8,8), tol 1e-8: t- and st-HOSVD-ALS."""
+    tk = gpu_lib
+    w = synth.workload_small_fp64()
+    A, ranks, tol = w["A"], w["ranks"], w["tol"]
+    Ag = to_gpu(A, "f64")
+    for which in ("st", "t"):
+        flush(f"driver small fp64 {which}")
+        if which == "st":
+            G, Us, info = tk.als_sthosvd(Ag, ranks, tol=tol, seed=11)
+            ref = o.sthosvd_als(A, ranks, tol=tol, seed=11)
+        else:
+            G, Us, info = tk.als_thosvd(Ag, ranks, tol=tol, seed=11)
+            ref = o.thosvd_als(A, ranks, tol=tol, seed=11)
+        e_gpu = _relerr_of(A, G, Us)
+        e_ref = o.relerr(A, ref.G, ref.U)
+        assert abs(e_gpu - e_ref) <= 1e-10
+        for n in range(3):
+            assert np.max(o.principal_angles(np64(Us[n]), ref.U[n])) < 1e-6
+            assert info["iters"][n] == ref.info[n].iters
+            assert abs(info["resid"][n] - ref.info[n].resid) <= 1e-8 * ref.norm_a
+        assert abs(info["norm_a"] - ref.norm_a) <= 1e-12 * ref.norm_a
+
+
+DRIVER_CASES = [
+    # dims, ranks, noise, order
+    ((24, 30, 36, 20), (6, 5, 7, 4), 1e-4, None),
+    ((70, 66, 40), (12, 9, 10), 1e-3, [2, 0, 1]),
+    ((130, 20, 33), (16, 8, 8), 1e-3, None),
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("dims,ranks,noise,order", DRIVER_CASES)
+@pytest.mark.parametrize("which", ["st", "t"])
+def test_driver_parity(gpu_lib, dims, ranks, noise, order, dt, which):
+    tk = gpu_lib
+    flush(f"driver {which} {dims} {ranks} {dt}")
+    rng = np.random.default_rng(20)
+    A, A0, _, _ = synth.tucker_lowrank(rng, dims, ranks, noise)
+    Ah = held(A, dt) if dt == "f32" else A
+    tol = 1e-6
+    if which == "st":
+        G, Us, info = tk.als_sthosvd(to_gpu(A, dt), ranks, tol=tol, seed=3, order=order)
+        ref = o.sthosvd_als(Ah, ranks, order=order, tol=tol, seed=3)
+    else:
+        G, Us, info = tk.als_thosvd(to_gpu(A, dt), ranks, tol=tol, seed=3)
+        ref = o.thosvd_als(Ah, ranks, tol=tol, seed=3)
+    e_gpu = _relerr_of(Ah, G, Us)
+    e_ref = o.relerr(Ah, ref.G, ref.U)
+    gate = 1e-5 if dt == "f32" else 1e-2
+    assert abs(e_gpu - e_ref) <= gate, (e_gpu, e_ref)
+    for U in Us:
+        Uh = np64(U)
+        np.testing.assert_allclose(Uh.T @ Uh, np.eye(Uh.shape[1]), atol=1e-5)
+
+
+def test_rank_deficient_status(gpu_lib):
+    tk = gpu_lib
+    rng = np.random.default_rng(30)
+    A = synth.tucker_lowrank(rng, (20, 22, 24), (3, 3, 3), 0.0)[0]
+    with pytest.raises(tk.TuckerALSError) as e:
+        tk.als_sthosvd(to_gpu(A, "f64"), (6, 3, 3), tol=1e-6)
+    assert e.value.code == -4
+
+
+def test_not_converged_status(gpu_lib):
+    tk = gpu_lib
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((30, 30, 30))
+    G, Us, info = tk.als_sthosvd(to_gpu(A, "f64"), (5, 5, 5), tol=1e-15, max_iters=2)
+    assert info["status"] == "TK_NOT_CONVERGED"
+    assert info["iters"][0] == 2 and not info["converged"][0]
+
+
+def test_nonfinite_input(gpu_lib):
+    tk = gpu_lib
+    A = np.ones((8, 9, 10))
+    A[3, 4, 5] = np.nan
+    with pytest.raises(tk.TuckerALSError) as e:
+        tk.als_sthosvd(to_gpu(A, "f32"), (2, 2, 2))
+    assert e.value.code == -5
+
+
+def test_full_rank_mode_identity(gpu_lib):
+    tk = gpu_lib
+    rng = np.random.default_rng(32)
+    A = rng.standard_normal((4, 9, 8))
+    G, Us, info = tk.als_sthosvd(to_gpu(A, "f64"), (4, 3, 5), tol=1e-8)
+    np.testing.assert_array_equal(np64(Us[0]), np.eye(4))
+    ref = o.sthosvd_als(A, (4, 3, 5), tol=1e-8)
+    assert abs(_relerr_of(A, G, Us) - o.relerr(A, ref.G, ref.U)) <= 1e-10
+
+
+def test_determinism(gpu_lib):
+    tk = gpu_lib
+    rng = np.random.default_rng(33)
+    A = to_gpu(rng.standard_normal((40, 50, 60)), "f32")
+    G1, U1, _ = tk.als_sthosvd(A, (5, 6, 7), tol=1e-6)
+    G2, U2, _ = tk.als_sthosvd(A, (5, 6, 7), tol=1e-6)
+    assert torch.equal(G1, G2) and all(torch.equal(a, b) for a, b in zip(U1, U2))
+
+
+KERNEL_CASES = [
+    # dims, mode, R : covers Q > 64, medium Q, Q == 1, ragged tiles, I > 256
+    ((200, 40, 30), 0, 20),     # P == 1, Q = 1200
+    ((20, 200, 50), 1, 20),     # Q = 50 < 64: tiles straddle p
+    ((30, 40, 200), 2, 20),     # Q == 1 (last mode)
+    ((17, 33, 65), 1, 3),       # R not a multiple of 4, ragged everything
+    ((64, 256, 9), 1, 32),      # I = 256, R = 32
+    ((9, 100, 70), 1, 48),      # R = 48 (largest fused rank)
+    ((300, 20, 40), 0, 12),     # I > 256: two-pass kernels
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("dims,mode,R", KERNEL_CASES)
+def test_sweep_kernel_parity(gpu_lib, dims, mode, R, dt):
+    """Lacc = A_(n) V and GV = V^T V for V = A_(n)^T Lq, against FP64 on the
+    same values (FP32 accumulation: a few roundings of I-term and
+    J-term sums)."""
+    tk = gpu_lib
+    flush(f"sweep_kernel {dims} mode={mode} R={R} {dt}")
+    rng = np.random.default_rng(40)
+    A = rng.standard_normal(dims)
+    Lq = rng.standard_normal((dims[mode], R)).astype(np.float32)
+    Lacc, GV = tk.als_sweep_kernel(to_gpu(A, dt), mode, torch.from_numpy(Lq).cuda())
+    An = o.unfold(held(A, dt), mode)
+    V = An.T @ Lq.astype(np.float64)
+    want_l = An @ V
+    want_g = V.T @ V
+    # scale-aware bounds: |V| from |A||Lq|, then |A||V|
+    Vabs = np.abs(An).T @ np.abs(Lq.astype(np.float64))
+    bl = (dims[mode] + 64) * 2.0 ** -24 * (np.abs(An) @ Vabs)
+    bg = (dims[mode] + 64) * 2.0 ** -24 * (Vabs.T @ Vabs)
+    assert np.all(np.abs(np64(Lacc) - want_l) <= 4 * bl + 1e-30)
+    assert np.all(np.abs(np64(GV) - want_g) <= 4 * bg + 1e-30)
+    np.testing.assert_array_equal(np64(GV), np64(GV).T)
+
+
+def test_two_pass_driver_parity(gpu_lib):
+    """I_1 = 300 > 256 runs the two-pass kernels for mode 1."""
+    tk = gpu_lib
+    rng = np.random.default_rng(41)
+    A = synth.tucker_lowrank(rng, (300, 24, 20), (10, 6, 8), 1e-3)[0]
+    Ah = held(A, "f32")
+    G, Us, info = tk.als_sthosvd(to_gpu(A, "f32"), (10, 6, 8), tol=1e-6, seed=5)
+    ref = o.sthosvd_als(Ah, (10, 6, 8), tol=1e-6, seed=5)
+    assert abs(_relerr_of(Ah, G, Us) - o.relerr(Ah, ref.G, ref.U)) <= 1e-5

@@ -157,3 +157,44 @@ def workload_batched(count=512, lo=16, hi=128, rlo=4, rhi=16, noise_rel=1e-3,
         A, _, _, _ = tucker_lowrank(rng, dims, tuple(ranks), noise_rel)
         items.append(dict(A=A, ranks=tuple(ranks)))
     return items
+
+
+# ---------------------------------------------------------------------------
+# Device-side generation of the large workloads (same recipe, drawn with
+# torch on the GPU so multi-GB tensors never pass through the host).
+
+def tucker_lowrank_torch(k: int, dims, core_dims, noise_rel: float, decay=None,
+                         device="cuda", out_dtype=None):
+    """Core (numpy, seeded with rng_for(k)) times orthonormal factors plus
+    relative Gaussian noise drawn on ``device`` (torch generator seeded with
+    SEED_BASE + k), assembled in float64 and returned as ``out_dtype``
+    (default float64).  Returns (A, core, factors)."""
+    import torch
+    rng = rng_for(k)
+    G = rng.standard_normal(tuple(core_dims))
+    if decay is not None:
+        G = G * decay
+    Us = [orthonormal(rng, d, r) for d, r in zip(dims, core_dims)]
+    X = torch.from_numpy(G).to(device)
+    for n, U in enumerate(Us):
+        Ut = torch.from_numpy(U).to(device)
+        X = torch.movedim(torch.tensordot(Ut, X, dims=([1], [n])), 0, n).contiguous()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + k)
+    nrm0 = torch.linalg.vector_norm(X).item()
+    E = torch.randn(X.shape, generator=gen, device=device, dtype=torch.float64)
+    E *= noise_rel * nrm0 / torch.linalg.vector_norm(E).item()
+    X += E
+    del E
+    if out_dtype is not None:
+        X = X.to(out_dtype)
+    return X, G, Us
+
+
+def workload_4way_torch(dims=(200, 200, 200, 200), R=20, noise_rel=1e-4, device="cuda"):
+    """The 4th-order decaying-core workload generated on the device (FP32)."""
+    import torch
+    core = (R,) * 4
+    A, _, Us = tucker_lowrank_torch(1, dims, core, noise_rel, decay=decay_exp(core, 10.0),
+                                    device=device, out_dtype=torch.float32)
+    return dict(A=A, ranks=(R,) * 4, factors=Us)
