@@ -57,75 +57,68 @@ __host__ __device__ inline Lds lds_layout(int I, int RG, int mode) {
   return l;
 }
 
-// Prefetch of one tile into registers.  Every load is a wave-uniform base
-// plus a 32-bit per-lane byte offset, so one VGPR addresses all rows.
-//  Q > 1 : wave w loads rows ii = 4k + w, lane = fibre (coalesced along q);
-//          lanes past the last fibre read fibre j0 (in bounds) and are
-//          zeroed when stored to LDS.
-//  Q == 1: wave w loads fibres jj = w + 4k; lane + 64c = row, clamped to
-//          I-1 (rows >= I are never stored).
-template <typename T>
+// Prefetch of one tile into registers: a fixed number of unconditional
+// loads per lane whose row / fibre indices are clamped into the tensor, so
+// the compiler issues them back to back (duplicates of the clamped row hit
+// the caches; only the LDS stores are guarded).
+//  LAYOUT 0 (Q > 1): wave w loads rows ii = 4k + w (k < 64) of fibre
+//          j0 + lane (coalesced along q); lanes past the last fibre read
+//          fibre j0 and are zeroed in the stash.
+//  LAYOUT 1 (Q == 1): wave w loads fibres jj = w + 4k (k < 16), rows
+//          lane + 64c (c < 4) of each contiguous fibre.
+template <typename T, int LAYOUT>
 __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v, int64_t j0,
                                          int lane, int w, T* pf, bool& ok) {
   const int64_t J = v.J();
   const int I = (int)v.I;
-  if (v.Q != 1) {
+  if (LAYOUT == 0) {
     const int64_t j = j0 + lane;
     ok = j < J;
-    const int64_t fb0 = v.fibre_base(j0);
-    const uint32_t voff = ok ? (uint32_t)((v.fibre_base(j) - fb0) * (int64_t)sizeof(T)) : 0u;
-    const char* base = (const char*)(X + fb0 + (int64_t)w * v.Q);
-    const int64_t step = 4 * v.Q * (int64_t)sizeof(T);
+    const int64_t base = v.fibre_base(ok ? j : j0);
+    const T* b = X + base;
 #pragma unroll
     for (int k = 0; k < 64; ++k) {
-      if (4 * k + w < I) pf[k] = *(const T*)(base + voff);
-      base += step;
+      const int ii = min(4 * k + w, I - 1);
+      pf[k] = b[(int64_t)ii * v.Q];
     }
   } else {
     ok = true;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int64_t j = j0 + w + 4 * k;
+      const int64_t j = min(j0 + w + 4 * k, J - 1);
+      const T* b = X + j * I;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (64 * c < I) {
-          if (j < J) {
-            const char* base = (const char*)(X + j * I + 64 * c);
-            const int ii = (lane + 64 * c < I) ? lane : I - 1 - 64 * c;
-            pf[4 * k + c] = *(const T*)(base + (uint32_t)(ii * (int)sizeof(T)));
-          } else {
-            pf[4 * k + c] = (T)0;
-          }
-        }
-      }
+      for (int c = 0; c < 4; ++c) pf[4 * k + c] = b[min(lane + 64 * c, I - 1)];
     }
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void stash(const View& v, int lane, int w, const T* pf, bool ok,
-                                      float* Xs) {
+template <typename T, int LAYOUT>
+__device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w, const T* pf,
+                                      bool ok, float* Xs) {
   const int I = (int)v.I;
-  if (v.Q != 1) {
+  if (LAYOUT == 0) {
 #pragma unroll
     for (int k = 0; k < 64; ++k) {
       const int ii = 4 * k + w;
       if (ii < I) Xs[ii * XLD + lane] = ok ? to_f<T>(pf[k]) : 0.0f;
     }
   } else {
+    const int64_t J = v.J();
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
+      const bool fok = j0 + w + 4 * k < J;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int ii = lane + 64 * c;
-        if (ii < I) Xs[ii * XLD + w + 4 * k] = to_f<T>(pf[4 * k + c]);
+        if (ii < I) Xs[ii * XLD + w + 4 * k] = fok ? to_f<T>(pf[4 * k + c]) : 0.0f;
       }
     }
   }
 }
 
 // MODE 0: sweep; 1: sweep + explicit residual; 2: init (sketch, no Gram).
-template <typename T, int RG, int MODE>
+template <typename T, int RG, int MODE, int LAYOUT>
 __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   extern __shared__ float smem[];
   constexpr int RP = 4 * RG;
@@ -188,26 +181,47 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   T pf[64];
   bool pf_ok = false;
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) prefetch<T>(X, v, tile * TJ, lane, w, pf, pf_ok);
+  if (tile < ntiles) prefetch<T, LAYOUT>(X, v, tile * TJ, lane, w, pf, pf_ok);
 
   for (; tile < ntiles; tile += nwg) {
     const int64_t j0 = tile * TJ;
     __syncthreads();
-    stash<T>(v, lane, w, pf, pf_ok, Xs);
+    stash<T, LAYOUT>(v, j0, lane, w, pf, pf_ok, Xs);
     __syncthreads();
-    if (tile + nwg < ntiles) prefetch<T>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
+    if (tile + nwg < ntiles) prefetch<T, LAYOUT>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
 
     if (MODE != 2) {
       // R-update partial over this wave's rows: V_w[j][r], lane = fibre j.
+      // Four rows per step; the LDS operands of step s+1 are read before
+      // the MFMAs of step s.  Rows past the wave's range get a zero B.
       f4 vacc[RG];
 #pragma unroll
       for (int g = 0; g < RG; ++g) vacc[g] = f4{0, 0, 0, 0};
-      for (int k = 0; k < IWw; ++k) {
-        const int i = i0 + k;
-        const float b = Xs[i * XLD + lane];
-        const float* lq = Lq + i * RP + l4 * RG;
+      float bc[4], lc[4][RG], bn[4], ln[4][RG];
+      auto rows4 = [&](int k, float (&b)[4], float (&l)[4][RG]) {
 #pragma unroll
-        for (int g = 0; g < RG; ++g) vacc[g] = mfma4(lq[g], b, vacc[g]);
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k + u;
+          const int i = i0 + (kk < IWw ? kk : 0);
+          b[u] = (kk < IWw) ? Xs[i * XLD + lane] : 0.0f;
+          const float* lq = Lq + i * RP + l4 * RG;
+#pragma unroll
+          for (int g = 0; g < RG; ++g) l[u][g] = lq[g];
+        }
+      };
+      rows4(0, bc, lc);
+      for (int k = 0; k < IWw; k += 4) {
+        rows4(k + 4, bn, ln);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int g = 0; g < RG; ++g) vacc[g] = mfma4(lc[u][g], bc[u], vacc[g]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          bc[u] = bn[u];
+#pragma unroll
+          for (int g = 0; g < RG; ++g) lc[u][g] = ln[u][g];
+        }
       }
       float* vp = Vp + (w * TJ + lane) * VS;
 #pragma unroll
@@ -242,19 +256,38 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     __syncthreads();
 
     // L-update: L_acc[i0 + lane-row][r] += X[i][j] V[j][r], lane = mode row.
-    for (int jl = 0; jl < TJ; ++jl) {
-      const float x = Xs[(i0 + lane) * XLD + jl];
-      const float* vf = Vf + jl * VS + l4 * RG;
+    // Operands of four fibres are read before their MFMAs.
 #pragma unroll
-      for (int g = 0; g < RG; ++g) lacc[g] = mfma4(x, vf[g], lacc[g]);
+    for (int jb = 0; jb < TJ; jb += 4) {
+      float x[4], vv[4][RG];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = Xs[(i0 + lane) * XLD + jb + u];
+        const float* vf = Vf + (jb + u) * VS + l4 * RG;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) vv[u][g] = vf[g];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int g = 0; g < RG; ++g) lacc[g] = mfma4(x[u], vv[u][g], lacc[g]);
     }
 
     if (MODE != 2) {
       // Gram of this wave's 16 fibres, FP32 within the tile, FP64 across.
-      for (int jl = 16 * w; jl < 16 * w + 16; ++jl) {
-        const float* vf = Vf + jl * VS + l4 * RG;
 #pragma unroll
-        for (int m = 0; m < NM; ++m) gacc[m] = mfma4(vf[gbi[m]], vf[gbj[m]], gacc[m]);
+      for (int jb = 16 * w; jb < 16 * w + 16; jb += 8) {
+        float ga[8][NM], gb[8][NM];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float* vf = Vf + (jb + u) * VS + l4 * RG;
+#pragma unroll
+          for (int m = 0; m < NM; ++m) { ga[u][m] = vf[gbi[m]]; gb[u][m] = vf[gbj[m]]; }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int m = 0; m < NM; ++m) gacc[m] = mfma4(ga[u][m], gb[u][m], gacc[m]);
       }
 #pragma unroll
       for (int m = 0; m < NM; ++m) {
@@ -322,45 +355,50 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
 }
 
+template <typename T, int RG, int MODE>
+void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
+  if (a.v.Q != 1) {
+    hipFuncSetAttribute((const void*)k_fused<T, RG, MODE, 0>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL((k_fused<T, RG, MODE, 0>), dim3(nwg), dim3(NT), bytes, s, a);
+  } else {
+    hipFuncSetAttribute((const void*)k_fused<T, RG, MODE, 1>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL((k_fused<T, RG, MODE, 1>), dim3(nwg), dim3(NT), bytes, s, a);
+  }
+}
+
 template <typename T, int RG>
 int launch_rg(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
   const Lds L = lds_layout((int)a.v.I, RG, mode);
   const size_t bytes = (size_t)L.total * 4;
-  if (mode == 0) {
-    hipFuncSetAttribute((const void*)k_fused<T, RG, 0>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, RG, 0>), dim3(nwg), dim3(NT), bytes, s, a);
-  } else if (mode == 1) {
-    hipFuncSetAttribute((const void*)k_fused<T, RG, 1>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, RG, 1>), dim3(nwg), dim3(NT), bytes, s, a);
-  } else {
-    hipFuncSetAttribute((const void*)k_fused<T, RG, 2>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, RG, 2>), dim3(nwg), dim3(NT), bytes, s, a);
-  }
+  if (mode == 0) launch_mode<T, RG, 0>(a, nwg, bytes, s);
+  else if (mode == 1) launch_mode<T, RG, 1>(a, nwg, bytes, s);
+  else launch_mode<T, RG, 2>(a, nwg, bytes, s);
   return nwg;
+}
+
+// R is padded up to 4*RG with RG from a fixed list (zero columns).
+inline int rg_of(int R) {
+  const int g = (R + 3) / 4;
+  if (g <= 6) return g;
+  if (g <= 8) return 8;
+  if (g <= 10) return 10;
+  return 12;
 }
 
 template <typename T>
 int launch_t(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
-  switch ((a.R + 3) / 4) {
+  switch (rg_of(a.R)) {
     case 1: return launch_rg<T, 1>(a, mode, nwg, s);
     case 2: return launch_rg<T, 2>(a, mode, nwg, s);
     case 3: return launch_rg<T, 3>(a, mode, nwg, s);
     case 4: return launch_rg<T, 4>(a, mode, nwg, s);
     case 5: return launch_rg<T, 5>(a, mode, nwg, s);
     case 6: return launch_rg<T, 6>(a, mode, nwg, s);
-    case 7: return launch_rg<T, 7>(a, mode, nwg, s);
     case 8: return launch_rg<T, 8>(a, mode, nwg, s);
-    case 9: return launch_rg<T, 9>(a, mode, nwg, s);
     case 10: return launch_rg<T, 10>(a, mode, nwg, s);
-    case 11: return launch_rg<T, 11>(a, mode, nwg, s);
     case 12: return launch_rg<T, 12>(a, mode, nwg, s);
-    case 13: return launch_rg<T, 13>(a, mode, nwg, s);
-    case 14: return launch_rg<T, 14>(a, mode, nwg, s);
-    case 15: return launch_rg<T, 15>(a, mode, nwg, s);
-    case 16: return launch_rg<T, 16>(a, mode, nwg, s);
   }
   return 0;
 }
@@ -372,9 +410,7 @@ constexpr int LDS_MAX_BYTES = 160 * 1024;
 bool fused_supported(int x_dtype, const View& v, int R, int resid_mode) {
   if (x_dtype != TK_F32 && x_dtype != TK_BF16) return false;
   if (v.I > 256 || v.I < 1 || R < 1 || R > 48) return false;
-  // per-lane byte offsets within a 64-fibre tile must fit in 32 bits
-  if ((double)(v.I + 1) * (double)v.Q * 4.0 >= 4294967296.0) return false;
-  const int RG = (R + 3) / 4;
+  const int RG = rg_of(R);
   const int mode = resid_mode == TK_RESID_EXPLICIT ? 1 : 0;
   return (size_t)lds_layout((int)v.I, RG, mode).total * 4 <= (size_t)LDS_MAX_BYTES;
 }

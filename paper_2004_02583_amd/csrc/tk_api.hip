@@ -330,49 +330,40 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
 // ---------------------------------------------------------------------------
 // Workspace plan of the drivers.
 
-size_t max_mode_ws(int xdt, int N, const int64_t* dims_in, const int32_t* ranks, bool st,
-                   const int32_t* order) {
-  // measure every mode solve at the shape it runs on
-  int64_t dims[TK_MAX_ORDER];
-  for (int k = 0; k < N; ++k) dims[k] = dims_in[k];
+// Workspace bound of a mode solve over every mode at the untruncated shape
+// (the largest view a mode can be solved on, whatever the st-HOSVD order),
+// in the storage dtype and, for st-HOSVD, the compute dtype of the
+// truncated intermediates.
+size_t max_mode_ws(int xdt, int N, const int64_t* dims, const int32_t* ranks, bool st) {
   size_t mx = 0;
-  for (int t = 0; t < N; ++t) {
-    int n = order ? order[t] : t;
+  for (int n = 0; n < N; ++n) {
     View v = mode_view(N, dims, n);
-    Arena ar(nullptr, (size_t)-1);
-    ModeWs w;
-    carve_mode(ar, st ? cdtype(xdt) == TK_F64 ? xdt : (t == 0 ? xdt : TK_F32) : xdt, v,
-               ranks[n], w);
-    mx = std::max(mx, ar.off);
-    if (st) dims[n] = ranks[n];
+    for (int pass = 0; pass < (st ? 2 : 1); ++pass) {
+      Arena ar(nullptr, (size_t)-1);
+      ModeWs w;
+      carve_mode(ar, pass == 0 ? xdt : cdtype(xdt), v, ranks[n], w);
+      mx = std::max(mx, ar.off);
+    }
   }
   return mx;
 }
 
-// Bytes of the ping-pong buffers holding intermediate tensors of a TTM chain.
-void chain_sizes(int N, const int64_t* dims_in, const int32_t* ranks, const int32_t* order,
-                 int64_t* maxa, int64_t* maxb) {
-  int64_t dims[TK_MAX_ORDER];
-  for (int k = 0; k < N; ++k) dims[k] = dims_in[k];
-  *maxa = 1; *maxb = 1;
-  for (int t = 0; t < N - 1; ++t) {
-    int n = order ? order[t] : t;
-    dims[n] = ranks[n];
-    int64_t e = numel(N, dims);
-    if (t % 2 == 0) *maxa = std::max(*maxa, e);
-    else *maxb = std::max(*maxb, e);
-  }
+// Elements of each ping-pong buffer holding intermediate tensors of a TTM
+// chain: bounded by the largest single-mode truncation of the input, which
+// covers every processing order.
+int64_t chain_elems(int N, const int64_t* dims, const int32_t* ranks) {
+  int64_t tot = numel(N, dims), mx = 1;
+  for (int n = 0; n < N; ++n) mx = std::max(mx, tot / dims[n] * ranks[n]);
+  return mx;
 }
 
-size_t driver_ws(int which, int xdt, int N, const int64_t* dims, const int32_t* ranks,
-                 const int32_t* order) {
-  size_t mw = max_mode_ws(xdt, N, dims, ranks, which == 1, order);
-  int64_t ea, eb;
-  chain_sizes(N, dims, ranks, order, &ea, &eb);
+size_t driver_ws(int which, int xdt, int N, const int64_t* dims, const int32_t* ranks) {
+  size_t mw = max_mode_ws(xdt, N, dims, ranks, which == 1);
   const size_t cs = dsize(cdtype(xdt));
+  const int64_t e = chain_elems(N, dims, ranks);
   size_t u64 = 0;
   for (int n = 0; n < N; ++n) u64 += align_up((size_t)dims[n] * ranks[n] * 8);
-  return align_up(mw) + align_up(ea * cs) + align_up(eb * cs) + u64 + 4096;
+  return align_up(mw) + 2 * align_up(e * cs) + u64 + 4096;
 }
 
 int ttm_enqueue(const void* X, int xdt, int N, const int64_t* dims, int mode, const void* M,
@@ -401,17 +392,16 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   int rc = read_opts(opts, N, o);
   if (rc) return rc;
   const int32_t* order = which == 1 ? o.order : nullptr;
-  size_t need = driver_ws(which, adt, N, dims, ranks, order);
+  size_t need = driver_ws(which, adt, N, dims, ranks);
   if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
 
   hipStream_t s = (hipStream_t)stream;
   const int cdt = cdtype(adt);
   const size_t cs = dsize(cdt);
-  int64_t ea, eb;
-  chain_sizes(N, dims, ranks, order, &ea, &eb);
+  const int64_t ech = chain_elems(N, dims, ranks);
   Arena ar(ws, ws_bytes);
-  void* bufA = ar.take(ea * cs);
-  void* bufB = ar.take(eb * cs);
+  void* bufA = ar.take(ech * cs);
+  void* bufB = ar.take(ech * cs);
   double* U64[TK_MAX_ORDER];
   for (int n = 0; n < N; ++n) U64[n] = (double*)ar.take((size_t)dims[n] * ranks[n] * 8);
   Arena mar(ar.base + ar.off, ar.cap - ar.off);
@@ -523,7 +513,7 @@ size_t als_workspace_bytes(int32_t which, int32_t a_dtype, int32_t N, const int6
   if ((which != 0 && which != 1) || !valid_dtype(a_dtype) || !valid_dims(N, dims) ||
       !valid_ranks(N, dims, ranks))
     return 0;
-  return driver_ws(which, a_dtype, N, dims, ranks, nullptr);
+  return driver_ws(which, a_dtype, N, dims, ranks);
 }
 
 int als_sthosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
@@ -739,7 +729,7 @@ size_t als_sthosvd_batched_workspace_bytes(int32_t count, const int64_t* dims3,
   for (int t = 0; t < count; ++t) {
     if (!valid_dims(3, dims3 + 3 * t) || !valid_ranks(3, dims3 + 3 * t, ranks3 + 3 * t))
       return 0;
-    mx = std::max(mx, driver_ws(1, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t, nullptr));
+    mx = std::max(mx, driver_ws(1, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t));
   }
   return mx;
 }
