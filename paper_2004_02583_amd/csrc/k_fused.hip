@@ -4,21 +4,21 @@
 // a_j (a column of A_(n)) from HBM once and uses it twice (row-wise update
 // rule of Section 3):
 //    v_j   = Lq^T a_j                (row j of R_k; never written out)
-//    G_V  += v_j v_j^T               (R_k^T R_k, flushed to FP64 per tile)
+//    G_V  += v_j v_j^T               (R_k^T R_k, FP32 per tile, FP64 across)
 //    L_acc += a_j v_j^T              (A_(n) R_k, per-workgroup partial)
-// and optionally accumulates the explicit residual sum_j ||a_j - L v_j||^2.
-// The init variant replaces v_j by row j of the Section 5 sketch S.
+// and optionally the explicit residual sum_j ||a_j - L v_j||^2.  The init
+// variant replaces v_j by row j of the Section 5 sketch S.
 //
-// Work layout: a workgroup of 4 waves walks 64-fibre tiles (persistent grid).
-// The tile X (I x 64, FP32 in LDS) is filled from registers that were
-// prefetched during the previous tile.  Wave w owns mode rows
-// [w*IW, (w+1)*IW), IW = ceil(I/4):
-//   R-update  v_mfma_f32_4x4x1f32, 16 blocks, lane = fibre, 4 r per block:
-//             K-split over the wave's rows, partials summed through LDS;
-//   L-update  same instruction, lane = mode row, 4 r per block, one fibre
-//             per instruction;
-//   Gram      one instruction per fibre covers 16 upper-triangle 4x4 blocks.
-// All reductions are in a fixed order (deterministic, no atomics).
+// Work layout: a workgroup of 4 waves walks 64-fibre tiles (persistent grid,
+// tile = blockIdx + k * gridDim).  The tile X (I x 64) is staged in LDS as
+// FP32 from registers that were prefetched during the previous tile.  All
+// three products use v_mfma_f32_16x16x4f32 (A 16x4, B 4x16, D 16x16):
+//   R-update  wave w owns fibres 16w..16w+15: V_w = X_w^T Lq, K = I;
+//   L-update  16x16 output tiles (16 mode rows x 16 ranks), K = 64 fibres,
+//             tiles dealt round-robin over the waves;
+//   Gram      each wave: V_w^T V_w over its 16 fibres, upper block triangle.
+// R is padded with zero columns to a multiple of 16.  Every reduction has a
+// fixed order (deterministic, no atomics).
 #include "tk_kernels.h"
 
 namespace tk {
@@ -32,290 +32,295 @@ constexpr int TJ = 64;       // fibres per tile
 constexpr int XLD = 65;      // LDS row stride of the X tile
 constexpr int NWG = 256;     // persistent workgroups (one per CU)
 
-__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+// D = A B + C with A 16x4 (lane l: row l%16, k l/16), B 4x16 (lane l:
+// k l/16, column l%16), D 16x16 (lane l, element q: row 4(l/16)+q,
+// column l%16).
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 template <typename T> __device__ __forceinline__ float to_f(T x);
 template <> __device__ __forceinline__ float to_f<float>(float x) { return x; }
 template <> __device__ __forceinline__ float to_f<bf16_t>(bf16_t x) { return bf16_to_f32(x); }
 
+// Row stride of the rank-indexed LDS arrays: 16 mod 32 keeps the 16x16x4
+// operand reads (two row offsets per half-wave) on distinct banks.
+__host__ __device__ constexpr int rank_stride(int RP) { return (RP % 32 == 0) ? RP + 16 : RP; }
+
 struct Lds {
-  int xs, lq, lr, vp, vf, total;  // offsets in floats
+  int xs, lq, lr, vf, total;  // offsets in floats
 };
 
-__host__ __device__ inline Lds lds_layout(int I, int RG, int mode) {
-  const int IW = (I + 3) / 4;
-  const int RP = 4 * RG;
+__host__ __device__ inline Lds lds_layout(int I, int NR, int mode) {
+  const int RP = 16 * NR;
+  const int xrows = 16 * ((I + 15) / 16);
+  const int RS = rank_stride(RP);
   Lds l;
   l.xs = 0;
-  l.lq = l.xs + 4 * IW * XLD;
-  l.lr = l.lq + (mode != 2 ? I * RP : 0);
-  l.vp = l.lr + (mode == 1 ? 4 * IW * RP : 0);
-  l.vf = l.vp + (mode != 2 ? 4 * TJ * (RP + 1) : 0);
-  l.total = l.vf + TJ * (RP + 1);
+  l.lq = l.xs + (xrows + 1) * XLD;            // + spare row for the stash
+  l.lr = l.lq + (mode != 2 ? xrows * RS : 0);
+  l.vf = l.lr + (mode == 1 ? xrows * (RP + 1) : 0);
+  l.total = l.vf + TJ * RS;
   return l;
 }
 
 // Prefetch of one tile into registers: a fixed number of unconditional
-// loads per lane whose row / fibre indices are clamped into the tensor, so
-// the compiler issues them back to back (duplicates of the clamped row hit
-// the caches; only the LDS stores are guarded).
-//  LAYOUT 0 (Q > 1): wave w loads rows ii = 4k + w (k < 64) of fibre
-//          j0 + lane (coalesced along q); lanes past the last fibre read
-//          fibre j0 and are zeroed in the stash.
-//  LAYOUT 1 (Q == 1): wave w loads fibres jj = w + 4k (k < 16), rows
-//          lane + 64c (c < 4) of each contiguous fibre.
-template <typename T, int LAYOUT>
+// loads per lane (IC = 16, 32 or 64 row slots per wave, from the mode size
+// class) whose row / fibre indices are clamped into the tensor, so the
+// compiler issues them back to back without branches (duplicates of a
+// clamped row hit the caches).  Slots [k0, k1) are issued per call, which
+// lets the largest class split its loads in two batches and stay below the
+// 63 outstanding vector-memory operations a wave can count.
+//  LAYOUT 0 (Q > 1): slot k is row ii = 4k + w of fibre j0 + lane
+//          (coalesced along q); lanes past the last fibre read fibre j0 and
+//          are zeroed in the stash.
+//  LAYOUT 1 (Q == 1): slot k = 4f + c is rows lane + 64c of fibre
+//          j0 + w + 4f (IC/4 chunks of 64 rows per fibre, 16 fibres).
+template <typename T, int LAYOUT, int IC>
 __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v, int64_t j0,
-                                         int lane, int w, T* pf, bool& ok) {
+                                         int lane, int w, T* pf, bool& ok, int k0, int k1) {
   const int64_t J = v.J();
   const int I = (int)v.I;
   if (LAYOUT == 0) {
     const int64_t j = j0 + lane;
     ok = j < J;
-    const int64_t base = v.fibre_base(ok ? j : j0);
-    const T* b = X + base;
+    const T* b = X + v.fibre_base(ok ? j : j0);
 #pragma unroll
-    for (int k = 0; k < 64; ++k) {
-      const int ii = min(4 * k + w, I - 1);
-      pf[k] = b[(int64_t)ii * v.Q];
+    for (int k = 0; k < IC; ++k) {
+      if (k >= k0 && k < k1) {
+        const int ii = min(4 * k + w, I - 1);
+        pf[k] = b[(int64_t)ii * v.Q];
+      }
     }
   } else {
     ok = true;
+    constexpr int NC = IC / 16;             // 64-row chunks per fibre
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int64_t j = min(j0 + w + 4 * k, J - 1);
-      const T* b = X + j * I;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) pf[4 * k + c] = b[min(lane + 64 * c, I - 1)];
-    }
-  }
-}
-
-template <typename T, int LAYOUT>
-__device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w, const T* pf,
-                                      bool ok, float* Xs) {
-  const int I = (int)v.I;
-  if (LAYOUT == 0) {
-#pragma unroll
-    for (int k = 0; k < 64; ++k) {
-      const int ii = 4 * k + w;
-      if (ii < I) Xs[ii * XLD + lane] = ok ? to_f<T>(pf[k]) : 0.0f;
-    }
-  } else {
-    const int64_t J = v.J();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const bool fok = j0 + w + 4 * k < J;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int ii = lane + 64 * c;
-        if (ii < I) Xs[ii * XLD + w + 4 * k] = fok ? to_f<T>(pf[4 * k + c]) : 0.0f;
+    for (int k = 0; k < IC; ++k) {
+      if (k >= k0 && k < k1) {
+        const int f = k / NC, c = k % NC;
+        const int64_t j = min(j0 + w + 4 * f, J - 1);
+        pf[k] = X[j * I + min(lane + 64 * c, I - 1)];
       }
     }
   }
 }
 
+// Rows past I go to the spare row `xrows` of the X tile (no branches).
+template <typename T, int LAYOUT, int IC>
+__device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w, const T* pf,
+                                      bool ok, int xrows, float* Xs) {
+  const int I = (int)v.I;
+  if (LAYOUT == 0) {
+#pragma unroll
+    for (int k = 0; k < IC; ++k) {
+      const int ii = 4 * k + w;
+      const int row = ii < I ? ii : xrows;
+      Xs[row * XLD + lane] = ok ? to_f<T>(pf[k]) : 0.0f;
+    }
+  } else {
+    const int64_t J = v.J();
+    constexpr int NC = IC / 16;
+#pragma unroll
+    for (int k = 0; k < IC; ++k) {
+      const int f = k / NC, c = k % NC;
+      const bool fok = j0 + w + 4 * f < J;
+      const int ii = lane + 64 * c;
+      const int row = ii < I ? ii : xrows;
+      Xs[row * XLD + w + 4 * f] = fok ? to_f<T>(pf[k]) : 0.0f;
+    }
+  }
+}
+
 // MODE 0: sweep; 1: sweep + explicit residual; 2: init (sketch, no Gram).
-template <typename T, int RG, int MODE, int LAYOUT>
+template <typename T, int NR, int MODE, int LAYOUT, int IC>
 __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   extern __shared__ float smem[];
-  constexpr int RP = 4 * RG;
-  constexpr int VS = RP + 1;                 // V row stride (odd: no conflicts)
-  constexpr int NP = RG * (RG + 1) / 2;      // upper-triangle 4x4 blocks
-  constexpr int NM = (NP + 15) / 16;         // Gram instructions per fibre
+  constexpr int RP = 16 * NR;
+  constexpr int RS = rank_stride(RP);        // Lq / Vf row stride
+  constexpr int LRS = RP + 1;                // Lr row stride
+  constexpr int NG = NR * (NR + 1) / 2;      // Gram output tiles
+  constexpr int U2 = 4 * NR;                 // max L-update tiles per wave
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
-  const int lane = threadIdx.x & 63, l4 = lane & 3;
+  const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int IW = (I + 3) / 4;
-  const int i0 = w * IW;
-  const int iend = (i0 + IW < I) ? i0 + IW : I;
-  const int IWw = iend > i0 ? iend - i0 : 0;
-  const Lds L = lds_layout(I, RG, MODE);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int MT = (I + 15) / 16;              // 16-row tiles of the mode
+  const int KS = (I + 3) / 4;                // 4-row K steps of the R-update
+  const int xrows = 16 * MT;
+  const Lds L = lds_layout(I, NR, MODE);
   float* Xs = smem + L.xs;
   float* Lq = smem + L.lq;
   float* Lr = smem + L.lr;
-  float* Vp = smem + L.vp;
   float* Vf = smem + L.vf;
 
-  // ---- once per kernel: zero the X tile (pad rows stay zero), load Lq/Lr
-  for (int e = threadIdx.x; e < 4 * IW * XLD; e += NT) Xs[e] = 0.0f;
+  // ---- once per kernel: zero the X tile (rows >= I stay zero), load Lq/Lr
+  for (int e = threadIdx.x; e < (xrows + 1) * XLD; e += NT) Xs[e] = 0.0f;
   if (MODE != 2) {
-    // Lq[i][c*RG + g] = L~(i, 4g + c): a lane reads its RG values contiguously
-    for (int e = threadIdx.x; e < I * RP; e += NT) {
+    for (int e = threadIdx.x; e < xrows * RP; e += NT) {
       const int i = e / RP, r = e % RP;
-      Lq[i * RP + (r & 3) * RG + (r >> 2)] = (r < R) ? a.Lq[i * R + r] : 0.0f;
+      Lq[i * RS + r] = (i < I && r < R) ? a.Lq[i * R + r] : 0.0f;
     }
   }
   if (MODE == 1) {
-    for (int e = threadIdx.x; e < 4 * IW * RP; e += NT) {
+    for (int e = threadIdx.x; e < xrows * RP; e += NT) {
       const int i = e / RP, r = e % RP;
-      Lr[e] = (i < I && r < R) ? -a.Lr[i * R + r] : 0.0f;
+      Lr[i * LRS + r] = (i < I && r < R) ? -a.Lr[i * R + r] : 0.0f;
     }
   }
 
-  f4 lacc[RG];
+  // L-update tiles of this wave: t = w + 4u -> (row tile t / NR, rank tile t % NR)
+  const int nt2 = MT * NR;
+  const int cnt2 = nt2 > w ? (nt2 - w + 3) / 4 : 0;
+  f4 lacc[U2];
 #pragma unroll
-  for (int g = 0; g < RG; ++g) lacc[g] = f4{0, 0, 0, 0};
-  double gd[NM][4];
-  f4 gacc[NM];
-  int gbi[NM], gbj[NM];
+  for (int u = 0; u < U2; ++u) lacc[u] = f4{0, 0, 0, 0};
+  f4 gacc[NG];
+  double gd[NG][4];
 #pragma unroll
-  for (int m = 0; m < NM; ++m) {
-    gacc[m] = f4{0, 0, 0, 0};
-    gd[m][0] = gd[m][1] = gd[m][2] = gd[m][3] = 0.0;
-    int p = 16 * m + (lane >> 2), bi = 0;
-    if (p >= NP) p = 0;
-    while (p >= RG - bi) { p -= RG - bi; ++bi; }
-    gbi[m] = bi;
-    gbj[m] = bi + p;
+  for (int p = 0; p < NG; ++p) {
+    gacc[p] = f4{0, 0, 0, 0};
+    gd[p][0] = gd[p][1] = gd[p][2] = gd[p][3] = 0.0;
   }
   double rsum = 0.0;
 
   const T* X = (const T*)a.X;
   const int64_t ntiles = ceil_div(J, TJ);
   const int nwg = gridDim.x;
-  T pf[64];
+  // IC = 64 issues its loads as 48 + 16 (around the R-update)
+  constexpr int KA = IC == 64 ? 48 : IC;
+  T pf[IC];
   bool pf_ok = false;
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) prefetch<T, LAYOUT>(X, v, tile * TJ, lane, w, pf, pf_ok);
+  if (tile < ntiles) prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf, pf_ok, 0, IC);
 
   for (; tile < ntiles; tile += nwg) {
     const int64_t j0 = tile * TJ;
+    const bool more = tile + nwg < ntiles;
     __syncthreads();
-    stash<T, LAYOUT>(v, j0, lane, w, pf, pf_ok, Xs);
+    stash<T, LAYOUT, IC>(v, j0, lane, w, pf, pf_ok, xrows, Xs);
     __syncthreads();
-    if (tile + nwg < ntiles) prefetch<T, LAYOUT>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
+    if (more) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok, 0, KA);
 
     if (MODE != 2) {
-      // R-update partial over this wave's rows: V_w[j][r], lane = fibre j.
-      // Four rows per step; the LDS operands of step s+1 are read before
-      // the MFMAs of step s.  Rows past the wave's range get a zero B.
-      f4 vacc[RG];
+      // R-update for fibres 16w..16w+15: A = X^T (16 fibres x 4 rows),
+      // B = Lq (4 rows x 16 ranks).  Four K steps per stage; the operands of
+      // the next stage are read before the MFMAs of this one.
+      f4 vacc[NR];
 #pragma unroll
-      for (int g = 0; g < RG; ++g) vacc[g] = f4{0, 0, 0, 0};
-      float bc[4], lc[4][RG], bn[4], ln[4][RG];
-      auto rows4 = [&](int k, float (&b)[4], float (&l)[4][RG]) {
+      for (int n = 0; n < NR; ++n) vacc[n] = f4{0, 0, 0, 0};
+      const float* xa = Xs + lk * XLD + 16 * w + lr;
+      const float* lb = Lq + lk * RS + lr;
+      float ac[4], bc[4][NR], an[4], bn[4][NR];
+      auto stage = [&](int ks, float (&aa)[4], float (&bb)[4][NR]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int kk = k + u;
-          const int i = i0 + (kk < IWw ? kk : 0);
-          b[u] = (kk < IWw) ? Xs[i * XLD + lane] : 0.0f;
-          const float* lq = Lq + i * RP + l4 * RG;
+          const int k = (ks + u < KS) ? ks + u : 0;     // zero A past the rows
+          aa[u] = (ks + u < KS) ? xa[4 * k * XLD] : 0.0f;
 #pragma unroll
-          for (int g = 0; g < RG; ++g) l[u][g] = lq[g];
+          for (int n = 0; n < NR; ++n) bb[u][n] = lb[4 * k * RS + 16 * n];
         }
       };
-      rows4(0, bc, lc);
-      for (int k = 0; k < IWw; k += 4) {
-        rows4(k + 4, bn, ln);
+      stage(0, ac, bc);
+      for (int ks = 0; ks < KS; ks += 4) {
+        stage(ks + 4, an, bn);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int g = 0; g < RG; ++g) vacc[g] = mfma4(lc[u][g], bc[u], vacc[g]);
+          for (int n = 0; n < NR; ++n) vacc[n] = mfma16(ac[u], bc[u][n], vacc[n]);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          bc[u] = bn[u];
+          ac[u] = an[u];
 #pragma unroll
-          for (int g = 0; g < RG; ++g) lc[u][g] = ln[u][g];
+          for (int n = 0; n < NR; ++n) bc[u][n] = bn[u][n];
         }
       }
-      float* vp = Vp + (w * TJ + lane) * VS;
+      if (KA < IC && more)
+        prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok, KA, IC);
+      // V[16w + 4lk + q][16n + lr] = vacc[n][q]
 #pragma unroll
-      for (int g = 0; g < RG; ++g)
+      for (int n = 0; n < NR; ++n)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) vp[4 * g + q] = vacc[g][q];
-      __syncthreads();
-      // fixed-order sum of the four partials for fibres 16w..16w+15
-#pragma unroll
-      for (int k = 0; k < RG; ++k) {
-        const int e = lane + 64 * k;
-        const int jl = 16 * w + e / RP, r = e % RP;
-        float s = Vp[(0 * TJ + jl) * VS + r];
-        s += Vp[(1 * TJ + jl) * VS + r];
-        s += Vp[(2 * TJ + jl) * VS + r];
-        s += Vp[(3 * TJ + jl) * VS + r];
-        Vf[jl * VS + (r & 3) * RG + (r >> 2)] = s;
-      }
+        for (int q = 0; q < 4; ++q) Vf[(16 * w + 4 * lk + q) * RS + 16 * n + lr] = vacc[n][q];
     } else {
-      // init: V = the Section 5 sketch rows of this tile
-#pragma unroll
-      for (int k = 0; k < RG; ++k) {
-        const int e = lane + 64 * k;
+      if (KA < IC && more)
+        prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok, KA, IC);
+      // init: V = the Section 5 sketch rows of this tile (16 fibres per wave)
+      for (int e = lane; e < 16 * RP; e += 64) {
         const int jl = 16 * w + e / RP, r = e % RP;
         const int64_t j = j0 + jl;
         float s = 0.0f;
         if (j < J && r < R)
           s = sketch_value(a.seed, ((uint64_t)a.mode << 48) + (uint64_t)(j * R + r));
-        Vf[jl * VS + (r & 3) * RG + (r >> 2)] = s;
+        Vf[jl * RS + r] = s;
       }
     }
     __syncthreads();
 
-    // L-update: L_acc[i0 + lane-row][r] += X[i][j] V[j][r], lane = mode row.
-    // Operands of four fibres are read before their MFMAs.
+    // L-update: tile (m, n) += X[16m.., f] V[f, 16n..] over the 64 fibres.
+    // B (the V rows of every rank tile) is read once per tile.
+    {
+      float vb[NR][16];
 #pragma unroll
-    for (int jb = 0; jb < TJ; jb += 4) {
-      float x[4], vv[4][RG];
+      for (int n = 0; n < NR; ++n)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        x[u] = Xs[(i0 + lane) * XLD + jb + u];
-        const float* vf = Vf + (jb + u) * VS + l4 * RG;
+        for (int ks = 0; ks < 16; ++ks) vb[n][ks] = Vf[(4 * ks + lk) * RS + 16 * n + lr];
 #pragma unroll
-        for (int g = 0; g < RG; ++g) vv[u][g] = vf[g];
+      for (int u = 0; u < U2; ++u) {
+        if (u < cnt2) {
+          const int t = w + 4 * u;
+          const int m = t / NR, n = t % NR;
+          const float* xr = Xs + (16 * m + lr) * XLD + lk;
+          float xa4[16];
+#pragma unroll
+          for (int ks = 0; ks < 16; ++ks) xa4[ks] = xr[4 * ks];
+#pragma unroll
+          for (int ks = 0; ks < 16; ++ks) {
+            float bsel = vb[0][ks];
+#pragma unroll
+            for (int nn = 1; nn < NR; ++nn) bsel = (n == nn) ? vb[nn][ks] : bsel;
+            lacc[u] = mfma16(xa4[ks], bsel, lacc[u]);
+          }
+        }
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int g = 0; g < RG; ++g) lacc[g] = mfma4(x[u], vv[u][g], lacc[g]);
-    }
 
-    if (MODE != 2) {
-      // Gram of this wave's 16 fibres, FP32 within the tile, FP64 across.
+      if (MODE != 2) {
+        // Gram over this wave's 16 fibres (4 K steps), upper block triangle.
 #pragma unroll
-      for (int jb = 16 * w; jb < 16 * w + 16; jb += 8) {
-        float ga[8][NM], gb[8][NM];
+        for (int kk = 0; kk < 4; ++kk) {
+          float g[NR];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const float* vf = Vf + (jb + u) * VS + l4 * RG;
+          for (int n = 0; n < NR; ++n) g[n] = Vf[(16 * w + 4 * kk + lk) * RS + 16 * n + lr];
+          int p = 0;
 #pragma unroll
-          for (int m = 0; m < NM; ++m) { ga[u][m] = vf[gbi[m]]; gb[u][m] = vf[gbj[m]]; }
+          for (int na = 0; na < NR; ++na)
+#pragma unroll
+            for (int nb = na; nb < NR; ++nb, ++p) gacc[p] = mfma16(g[na], g[nb], gacc[p]);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int p = 0; p < NG; ++p) {
 #pragma unroll
-          for (int m = 0; m < NM; ++m) gacc[m] = mfma4(ga[u][m], gb[u][m], gacc[m]);
-      }
-#pragma unroll
-      for (int m = 0; m < NM; ++m) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) gd[m][q] += (double)gacc[m][q];
-        gacc[m] = f4{0, 0, 0, 0};
+          for (int q = 0; q < 4; ++q) gd[p][q] += (double)gacc[p][q];
+          gacc[p] = f4{0, 0, 0, 0};
+        }
       }
     }
 
     if (MODE == 1) {
-      // explicit residual: a_j - L v_j for this wave's rows, lane = fibre.
-      float vj[RP];
-      const float* vr = Vf + lane * VS;
+      // explicit residual of this wave's 16 fibres: D = X - L V^T per 16-row
+      // tile, A = -L (16 rows x 4 ranks), B = V^T (4 ranks x 16 fibres).
+      for (int m = 0; m < MT; ++m) {
+        f4 c;
 #pragma unroll
-      for (int g = 0; g < RG; ++g)
+        for (int q = 0; q < 4; ++q) c[q] = Xs[(16 * m + 4 * lk + q) * XLD + 16 * w + lr];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) vj[4 * g + c] = vr[c * RG + g];
-      for (int t = 0; t < IWw; t += 4) {
-        const int ib = i0 + t;
-        f4 c4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c4[q] = (t + q < IWw) ? Xs[(ib + q) * XLD + lane] : 0.0f;
-        const float* lr = Lr + (ib + l4) * RP;
-#pragma unroll
-        for (int r = 0; r < RP; ++r) c4 = mfma4(lr[r], vj[r], c4);
+        for (int ks = 0; ks < RP / 4; ++ks)
+          c = mfma16(Lr[(16 * m + lr) * LRS + 4 * ks + lk], Vf[(16 * w + lr) * RS + 4 * ks + lk], c);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (t + q < IWw) rsum += (double)c4[q] * (double)c4[q];
+          if (16 * m + 4 * lk + q < I) rsum += (double)c[q] * (double)c[q];
       }
     }
   }
@@ -324,26 +329,32 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   const int wg = blockIdx.x;
   float* lp = a.lacc_parts + (int64_t)wg * I * R;
 #pragma unroll
-  for (int g = 0; g < RG; ++g) {
+  for (int u = 0; u < U2; ++u) {
+    if (u < cnt2) {
+      const int t = w + 4 * u;
+      const int m = t / NR, n = t % NR;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = i0 + 4 * (lane >> 2) + q;
-      const int r = 4 * g + l4;
-      if (i < iend && r < R) lp[i * R + r] = lacc[g][q];
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * m + 4 * lk + q, r = 16 * n + lr;
+        if (i < I && r < R) lp[i * R + r] = lacc[u][q];
+      }
     }
   }
   if (MODE != 2) {
-    // the upper-triangle 4x4 blocks and their mirrors cover every entry
+    // the upper block triangle and its mirror cover every entry
     double* gp = a.gv_parts + (int64_t)(wg * 4 + w) * R * R;
+    int p = 0;
 #pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      if (16 * m + (lane >> 2) >= NP) continue;
+    for (int na = 0; na < NR; ++na) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = 4 * gbi[m] + q, col = 4 * gbj[m] + l4;
-        if (row < R && col < R) {
-          gp[row * R + col] = gd[m][q];
-          gp[col * R + row] = gd[m][q];
+      for (int nb = na; nb < NR; ++nb, ++p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * na + 4 * lk + q, col = 16 * nb + lr;
+          if (row < R && col < R) {
+            gp[row * R + col] = gd[p][q];
+            gp[col * R + row] = gd[p][q];
+          }
         }
       }
     }
@@ -355,50 +366,42 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
 }
 
-template <typename T, int RG, int MODE>
-void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
+template <typename T, int NR, int MODE, int IC>
+void launch_ic(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
   if (a.v.Q != 1) {
-    hipFuncSetAttribute((const void*)k_fused<T, RG, MODE, 0>,
+    hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, RG, MODE, 0>), dim3(nwg), dim3(NT), bytes, s, a);
+    hipLaunchKernelGGL((k_fused<T, NR, MODE, 0, IC>), dim3(nwg), dim3(NT), bytes, s, a);
   } else {
-    hipFuncSetAttribute((const void*)k_fused<T, RG, MODE, 1>,
+    hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 1, IC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, RG, MODE, 1>), dim3(nwg), dim3(NT), bytes, s, a);
+    hipLaunchKernelGGL((k_fused<T, NR, MODE, 1, IC>), dim3(nwg), dim3(NT), bytes, s, a);
   }
 }
 
-template <typename T, int RG>
-int launch_rg(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
-  const Lds L = lds_layout((int)a.v.I, RG, mode);
-  const size_t bytes = (size_t)L.total * 4;
-  if (mode == 0) launch_mode<T, RG, 0>(a, nwg, bytes, s);
-  else if (mode == 1) launch_mode<T, RG, 1>(a, nwg, bytes, s);
-  else launch_mode<T, RG, 2>(a, nwg, bytes, s);
-  return nwg;
+// Row-slot class: 16, 32 or 64 slots per wave (I <= 64, 128, 256).
+template <typename T, int NR, int MODE>
+void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
+  if (a.v.I <= 64) launch_ic<T, NR, MODE, 16>(a, nwg, bytes, s);
+  else if (a.v.I <= 128) launch_ic<T, NR, MODE, 32>(a, nwg, bytes, s);
+  else launch_ic<T, NR, MODE, 64>(a, nwg, bytes, s);
 }
 
-// R is padded up to 4*RG with RG from a fixed list (zero columns).
-inline int rg_of(int R) {
-  const int g = (R + 3) / 4;
-  if (g <= 6) return g;
-  if (g <= 8) return 8;
-  if (g <= 10) return 10;
-  return 12;
+template <typename T, int NR>
+int launch_nr(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
+  const size_t bytes = (size_t)lds_layout((int)a.v.I, NR, mode).total * 4;
+  if (mode == 0) launch_mode<T, NR, 0>(a, nwg, bytes, s);
+  else if (mode == 1) launch_mode<T, NR, 1>(a, nwg, bytes, s);
+  else launch_mode<T, NR, 2>(a, nwg, bytes, s);
+  return nwg;
 }
 
 template <typename T>
 int launch_t(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
-  switch (rg_of(a.R)) {
-    case 1: return launch_rg<T, 1>(a, mode, nwg, s);
-    case 2: return launch_rg<T, 2>(a, mode, nwg, s);
-    case 3: return launch_rg<T, 3>(a, mode, nwg, s);
-    case 4: return launch_rg<T, 4>(a, mode, nwg, s);
-    case 5: return launch_rg<T, 5>(a, mode, nwg, s);
-    case 6: return launch_rg<T, 6>(a, mode, nwg, s);
-    case 8: return launch_rg<T, 8>(a, mode, nwg, s);
-    case 10: return launch_rg<T, 10>(a, mode, nwg, s);
-    case 12: return launch_rg<T, 12>(a, mode, nwg, s);
+  switch ((a.R + 15) / 16) {
+    case 1: return launch_nr<T, 1>(a, mode, nwg, s);
+    case 2: return launch_nr<T, 2>(a, mode, nwg, s);
+    case 3: return launch_nr<T, 3>(a, mode, nwg, s);
   }
   return 0;
 }
@@ -410,9 +413,9 @@ constexpr int LDS_MAX_BYTES = 160 * 1024;
 bool fused_supported(int x_dtype, const View& v, int R, int resid_mode) {
   if (x_dtype != TK_F32 && x_dtype != TK_BF16) return false;
   if (v.I > 256 || v.I < 1 || R < 1 || R > 48) return false;
-  const int RG = rg_of(R);
+  const int NR = (R + 15) / 16;
   const int mode = resid_mode == TK_RESID_EXPLICIT ? 1 : 0;
-  return (size_t)lds_layout((int)v.I, RG, mode).total * 4 <= (size_t)LDS_MAX_BYTES;
+  return (size_t)lds_layout((int)v.I, NR, mode).total * 4 <= (size_t)LDS_MAX_BYTES;
 }
 
 int fused_workgroups(const View& v) {
