@@ -9,14 +9,16 @@
 // and optionally the explicit residual sum_j ||a_j - L v_j||^2.  The init
 // variant replaces v_j by row j of the Section 5 sketch S.
 //
-// Work layout: a workgroup of 4 waves walks 64-fibre tiles (persistent grid,
-// tile = blockIdx + k * gridDim).  The tile X (I x 64) is staged in LDS as
-// FP32 from registers that were prefetched during the previous tile.  All
-// three products use v_mfma_f32_16x16x4f32 (A 16x4, B 4x16, D 16x16):
-//   R-update  wave w owns fibres 16w..16w+15: V_w = X_w^T Lq, K = I;
+// Work layout: a workgroup of 8 waves (two per SIMD) walks 64-fibre tiles
+// (persistent grid, tile = blockIdx + k * gridDim).  The tile X (I x 64) is
+// staged in LDS as FP32 from registers that were prefetched during the
+// previous tile.  All three products use v_mfma_f32_16x16x4f32 (A 16x4,
+// B 4x16, D 16x16):
+//   R-update  16x16 output tiles (16 fibres x 16 ranks), K = I, dealt
+//             round-robin over the waves: V = X^T Lq;
 //   L-update  16x16 output tiles (16 mode rows x 16 ranks), K = 64 fibres,
-//             tiles dealt round-robin over the waves;
-//   Gram      each wave: V_w^T V_w over its 16 fibres, upper block triangle.
+//             dealt round-robin over the waves;
+//   Gram      wave w: V^T V over fibres 8w..8w+7, upper block triangle.
 // R is padded with zero columns to a multiple of 16.  Every reduction has a
 // fixed order (deterministic, no atomics).
 #include "tk_kernels.h"
@@ -27,7 +29,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int NT = 256;      // threads per workgroup
+constexpr int NT = 512;      // threads per workgroup
+constexpr int NW = NT / 64;  // waves per workgroup
+static_assert(NW == FUSED_WAVES, "partial buffers are sized for FUSED_WAVES waves");
 constexpr int TJ = 64;       // fibres per tile
 constexpr int XLD = 65;      // LDS row stride of the X tile
 constexpr int NWG = 256;     // persistent workgroups (one per CU)
@@ -65,20 +69,18 @@ __host__ __device__ inline Lds lds_layout(int I, int NR, int mode) {
 }
 
 // Prefetch of one tile into registers: a fixed number of unconditional
-// loads per lane (IC = 16, 32 or 64 row slots per wave, from the mode size
+// loads per lane (IC = 8, 16 or 32 row slots per wave, from the mode size
 // class) whose row / fibre indices are clamped into the tensor, so the
 // compiler issues them back to back without branches (duplicates of a
-// clamped row hit the caches).  Slots [k0, k1) are issued per call, which
-// lets the largest class split its loads in two batches and stay below the
-// 63 outstanding vector-memory operations a wave can count.
-//  LAYOUT 0 (Q > 1): slot k is row ii = 4k + w of fibre j0 + lane
+// clamped row hit the caches).
+//  LAYOUT 0 (Q > 1): slot k is row ii = 8k + w of fibre j0 + lane
 //          (coalesced along q); lanes past the last fibre read fibre j0 and
 //          are zeroed in the stash.
-//  LAYOUT 1 (Q == 1): slot k = 4f + c is rows lane + 64c of fibre
-//          j0 + w + 4f (IC/4 chunks of 64 rows per fibre, 16 fibres).
+//  LAYOUT 1 (Q == 1): slot k = NC f + c is rows lane + 64c of fibre
+//          j0 + w + 8f (NC = IC/8 chunks of 64 rows per fibre, 8 fibres).
 template <typename T, int LAYOUT, int IC>
 __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v, int64_t j0,
-                                         int lane, int w, T* pf, bool& ok, int k0, int k1) {
+                                         int lane, int w, T* pf, bool& ok) {
   const int64_t J = v.J();
   const int I = (int)v.I;
   if (LAYOUT == 0) {
@@ -87,21 +89,17 @@ __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v,
     const T* b = X + v.fibre_base(ok ? j : j0);
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
-      if (k >= k0 && k < k1) {
-        const int ii = min(4 * k + w, I - 1);
-        pf[k] = b[(int64_t)ii * v.Q];
-      }
+      const int ii = min(NW * k + w, I - 1);
+      pf[k] = b[(int64_t)ii * v.Q];
     }
   } else {
     ok = true;
-    constexpr int NC = IC / 16;             // 64-row chunks per fibre
+    constexpr int NC = IC / 8;              // 64-row chunks per fibre
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
-      if (k >= k0 && k < k1) {
-        const int f = k / NC, c = k % NC;
-        const int64_t j = min(j0 + w + 4 * f, J - 1);
-        pf[k] = X[j * I + min(lane + 64 * c, I - 1)];
-      }
+      const int f = k / NC, c = k % NC;
+      const int64_t j = min(j0 + w + NW * f, J - 1);
+      pf[k] = X[j * I + min(lane + 64 * c, I - 1)];
     }
   }
 }
@@ -114,20 +112,20 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
   if (LAYOUT == 0) {
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
-      const int ii = 4 * k + w;
+      const int ii = NW * k + w;
       const int row = ii < I ? ii : xrows;
       Xs[row * XLD + lane] = ok ? to_f<T>(pf[k]) : 0.0f;
     }
   } else {
     const int64_t J = v.J();
-    constexpr int NC = IC / 16;
+    constexpr int NC = IC / 8;
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
       const int f = k / NC, c = k % NC;
-      const bool fok = j0 + w + 4 * f < J;
+      const bool fok = j0 + w + NW * f < J;
       const int ii = lane + 64 * c;
       const int row = ii < I ? ii : xrows;
-      Xs[row * XLD + w + 4 * f] = fok ? to_f<T>(pf[k]) : 0.0f;
+      Xs[row * XLD + w + NW * f] = fok ? to_f<T>(pf[k]) : 0.0f;
     }
   }
 }
@@ -140,7 +138,9 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   constexpr int RS = rank_stride(RP);        // Lq / Vf row stride
   constexpr int LRS = RP + 1;                // Lr row stride
   constexpr int NG = NR * (NR + 1) / 2;      // Gram output tiles
-  constexpr int U2 = 4 * NR;                 // max L-update tiles per wave
+  constexpr int U1 = (4 * NR + NW - 1) / NW; // R-update tiles per wave (max)
+  constexpr int U2 = 2 * NR;                 // L-update tiles per wave (max)
+  constexpr bool NFIX = (NW % NR) == 0;      // a wave's L-update rank tile is fixed
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
@@ -171,9 +171,11 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     }
   }
 
-  // L-update tiles of this wave: t = w + 4u -> (row tile t / NR, rank tile t % NR)
+  // R-update tiles: t = w + NW u -> (fibre block t / NR, rank tile t % NR)
+  const int cnt1 = 4 * NR > w ? (4 * NR - w + NW - 1) / NW : 0;
+  // L-update tiles: t = w + NW u -> (row tile t / NR, rank tile t % NR)
   const int nt2 = MT * NR;
-  const int cnt2 = nt2 > w ? (nt2 - w + 3) / 4 : 0;
+  const int cnt2 = nt2 > w ? (nt2 - w + NW - 1) / NW : 0;
   f4 lacc[U2];
 #pragma unroll
   for (int u = 0; u < U2; ++u) lacc[u] = f4{0, 0, 0, 0};
@@ -189,67 +191,57 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   const T* X = (const T*)a.X;
   const int64_t ntiles = ceil_div(J, TJ);
   const int nwg = gridDim.x;
-  // IC = 64 issues its loads as 48 + 16 (around the R-update)
-  constexpr int KA = IC == 64 ? 48 : IC;
   T pf[IC];
   bool pf_ok = false;
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf, pf_ok, 0, IC);
+  if (tile < ntiles) prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf, pf_ok);
 
   for (; tile < ntiles; tile += nwg) {
     const int64_t j0 = tile * TJ;
-    const bool more = tile + nwg < ntiles;
     __syncthreads();
     stash<T, LAYOUT, IC>(v, j0, lane, w, pf, pf_ok, xrows, Xs);
     __syncthreads();
-    if (more) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok, 0, KA);
+    if (tile + nwg < ntiles) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
 
     if (MODE != 2) {
-      // R-update for fibres 16w..16w+15: A = X^T (16 fibres x 4 rows),
-      // B = Lq (4 rows x 16 ranks).  Four K steps per stage; the operands of
-      // the next stage are read before the MFMAs of this one.
-      f4 vacc[NR];
+      // R-update: tile (fibre block f, rank tile n): A = X^T (16 fibres x
+      // 4 rows), B = Lq (4 rows x 16 ranks), K = I in steps of 4.  Four K
+      // steps per stage; the next stage's operands are read first.
 #pragma unroll
-      for (int n = 0; n < NR; ++n) vacc[n] = f4{0, 0, 0, 0};
-      const float* xa = Xs + lk * XLD + 16 * w + lr;
-      const float* lb = Lq + lk * RS + lr;
-      float ac[4], bc[4][NR], an[4], bn[4][NR];
-      auto stage = [&](int ks, float (&aa)[4], float (&bb)[4][NR]) {
+      for (int u = 0; u < U1; ++u) {
+        if (u < cnt1) {
+          const int t = w + NW * u;
+          const int fb = t / NR, n = t % NR;
+          const float* xa = Xs + lk * XLD + 16 * fb + lr;
+          const float* lb = Lq + lk * RS + 16 * n + lr;
+          f4 vacc = f4{0, 0, 0, 0};
+          float ac[4], bc[4], an[4], bn[4];
+          auto stage = [&](int ks, float (&aa)[4], float (&bb)[4]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = (ks + u < KS) ? ks + u : 0;     // zero A past the rows
-          aa[u] = (ks + u < KS) ? xa[4 * k * XLD] : 0.0f;
+            for (int q = 0; q < 4; ++q) {
+              const bool in = ks + q < KS;
+              const int k = in ? ks + q : 0;
+              aa[q] = in ? xa[4 * k * XLD] : 0.0f;
+              bb[q] = lb[4 * k * RS];
+            }
+          };
+          stage(0, ac, bc);
+          for (int ks = 0; ks < KS; ks += 4) {
+            stage(ks + 4, an, bn);
 #pragma unroll
-          for (int n = 0; n < NR; ++n) bb[u][n] = lb[4 * k * RS + 16 * n];
-        }
-      };
-      stage(0, ac, bc);
-      for (int ks = 0; ks < KS; ks += 4) {
-        stage(ks + 4, an, bn);
+            for (int q = 0; q < 4; ++q) vacc = mfma16(ac[q], bc[q], vacc);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int q = 0; q < 4; ++q) { ac[q] = an[q]; bc[q] = bn[q]; }
+          }
+          // V[16 fb + 4 lk + q][16 n + lr] = vacc[q]
 #pragma unroll
-          for (int n = 0; n < NR; ++n) vacc[n] = mfma16(ac[u], bc[u][n], vacc[n]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ac[u] = an[u];
-#pragma unroll
-          for (int n = 0; n < NR; ++n) bc[u][n] = bn[u][n];
+          for (int q = 0; q < 4; ++q) Vf[(16 * fb + 4 * lk + q) * RS + 16 * n + lr] = vacc[q];
         }
       }
-      if (KA < IC && more)
-        prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok, KA, IC);
-      // V[16w + 4lk + q][16n + lr] = vacc[n][q]
-#pragma unroll
-      for (int n = 0; n < NR; ++n)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Vf[(16 * w + 4 * lk + q) * RS + 16 * n + lr] = vacc[n][q];
     } else {
-      if (KA < IC && more)
-        prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok, KA, IC);
-      // init: V = the Section 5 sketch rows of this tile (16 fibres per wave)
-      for (int e = lane; e < 16 * RP; e += 64) {
-        const int jl = 16 * w + e / RP, r = e % RP;
+      // init: V = the Section 5 sketch rows of this tile
+      for (int e = threadIdx.x; e < TJ * RP; e += NT) {
+        const int jl = e / RP, r = e % RP;
         const int64_t j = j0 + jl;
         float s = 0.0f;
         if (j < J && r < R)
@@ -260,17 +252,20 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     __syncthreads();
 
     // L-update: tile (m, n) += X[16m.., f] V[f, 16n..] over the 64 fibres.
-    // B (the V rows of every rank tile) is read once per tile.
     {
-      float vb[NR][16];
+      constexpr int NB = NFIX ? 1 : NR;        // rank tiles cached in registers
+      float vb[NB][16];
+      const int nfix = w % NR;
 #pragma unroll
-      for (int n = 0; n < NR; ++n)
+      for (int nn = 0; nn < NB; ++nn) {
+        const int n = NFIX ? nfix : nn;
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) vb[n][ks] = Vf[(4 * ks + lk) * RS + 16 * n + lr];
+        for (int ks = 0; ks < 16; ++ks) vb[nn][ks] = Vf[(4 * ks + lk) * RS + 16 * n + lr];
+      }
 #pragma unroll
       for (int u = 0; u < U2; ++u) {
         if (u < cnt2) {
-          const int t = w + 4 * u;
+          const int t = w + NW * u;
           const int m = t / NR, n = t % NR;
           const float* xr = Xs + (16 * m + lr) * XLD + lk;
           float xa4[16];
@@ -279,25 +274,29 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 #pragma unroll
           for (int ks = 0; ks < 16; ++ks) {
             float bsel = vb[0][ks];
+            if (!NFIX) {
 #pragma unroll
-            for (int nn = 1; nn < NR; ++nn) bsel = (n == nn) ? vb[nn][ks] : bsel;
+              for (int nn = 1; nn < NB; ++nn) bsel = (n == nn) ? vb[nn][ks] : bsel;
+            }
             lacc[u] = mfma16(xa4[ks], bsel, lacc[u]);
           }
         }
       }
 
       if (MODE != 2) {
-        // Gram over this wave's 16 fibres (4 K steps), upper block triangle.
+        // Gram over fibres 8w..8w+7 (2 K steps), upper block triangle.
+        float g[2][NR];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          float g[NR];
+        for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-          for (int n = 0; n < NR; ++n) g[n] = Vf[(16 * w + 4 * kk + lk) * RS + 16 * n + lr];
+          for (int n = 0; n < NR; ++n) g[kk][n] = Vf[(8 * w + 4 * kk + lk) * RS + 16 * n + lr];
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
           int p = 0;
 #pragma unroll
           for (int na = 0; na < NR; ++na)
 #pragma unroll
-            for (int nb = na; nb < NR; ++nb, ++p) gacc[p] = mfma16(g[na], g[nb], gacc[p]);
+            for (int nb = na; nb < NR; ++nb, ++p) gacc[p] = mfma16(g[kk][na], g[kk][nb], gacc[p]);
         }
 #pragma unroll
         for (int p = 0; p < NG; ++p) {
@@ -309,15 +308,17 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     }
 
     if (MODE == 1) {
-      // explicit residual of this wave's 16 fibres: D = X - L V^T per 16-row
-      // tile, A = -L (16 rows x 4 ranks), B = V^T (4 ranks x 16 fibres).
-      for (int m = 0; m < MT; ++m) {
+      // explicit residual: D = X - L V^T per (16-row tile m, fibre block fb),
+      // A = -L (16 rows x 4 ranks), B = V^T (4 ranks x 16 fibres); wave w
+      // takes fibre block w % 4 and row tiles m = w / 4 + 2k.
+      const int fb = w % 4;
+      for (int m = w / 4; m < MT; m += 2) {
         f4 c;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = Xs[(16 * m + 4 * lk + q) * XLD + 16 * w + lr];
+        for (int q = 0; q < 4; ++q) c[q] = Xs[(16 * m + 4 * lk + q) * XLD + 16 * fb + lr];
 #pragma unroll
         for (int ks = 0; ks < RP / 4; ++ks)
-          c = mfma16(Lr[(16 * m + lr) * LRS + 4 * ks + lk], Vf[(16 * w + lr) * RS + 4 * ks + lk], c);
+          c = mfma16(Lr[(16 * m + lr) * LRS + 4 * ks + lk], Vf[(16 * fb + lr) * RS + 4 * ks + lk], c);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (16 * m + 4 * lk + q < I) rsum += (double)c[q] * (double)c[q];
@@ -331,7 +332,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 #pragma unroll
   for (int u = 0; u < U2; ++u) {
     if (u < cnt2) {
-      const int t = w + 4 * u;
+      const int t = w + NW * u;
       const int m = t / NR, n = t % NR;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
   if (MODE != 2) {
     // the upper block triangle and its mirror cover every entry
-    double* gp = a.gv_parts + (int64_t)(wg * 4 + w) * R * R;
+    double* gp = a.gv_parts + (int64_t)(wg * NW + w) * R * R;
     int p = 0;
 #pragma unroll
     for (int na = 0; na < NR; ++na) {
@@ -362,7 +363,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   if (MODE == 1) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off, 64);
-    if (lane == 0) a.resid_parts[wg * 4 + w] = rsum;
+    if (lane == 0) a.resid_parts[wg * NW + w] = rsum;
   }
 }
 
@@ -379,12 +380,12 @@ void launch_ic(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
   }
 }
 
-// Row-slot class: 16, 32 or 64 slots per wave (I <= 64, 128, 256).
+// Row-slot class: 8, 16 or 32 slots per wave (I <= 64, 128, 256).
 template <typename T, int NR, int MODE>
 void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
-  if (a.v.I <= 64) launch_ic<T, NR, MODE, 16>(a, nwg, bytes, s);
-  else if (a.v.I <= 128) launch_ic<T, NR, MODE, 32>(a, nwg, bytes, s);
-  else launch_ic<T, NR, MODE, 64>(a, nwg, bytes, s);
+  if (a.v.I <= 64) launch_ic<T, NR, MODE, 8>(a, nwg, bytes, s);
+  else if (a.v.I <= 128) launch_ic<T, NR, MODE, 16>(a, nwg, bytes, s);
+  else launch_ic<T, NR, MODE, 32>(a, nwg, bytes, s);
 }
 
 template <typename T, int NR>
@@ -425,7 +426,7 @@ int fused_workgroups(const View& v) {
 
 int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s) {
   int nwg = fused_workgroups(a.v);
-  if (nwg > nwg_max / 4) nwg = nwg_max / 4;
+  if (nwg > nwg_max / NW) nwg = nwg_max / NW;
   const int mode = a.sketch ? 2 : (a.Lr ? 1 : 0);
   if (a.x_dtype == TK_F32) return launch_t<float>(a, mode, nwg, s);
   return launch_t<bf16_t>(a, mode, nwg, s);

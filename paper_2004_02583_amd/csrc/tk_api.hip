@@ -14,7 +14,7 @@
 namespace tk {
 namespace {
 
-constexpr int NWG_MAX = 1024;     // upper bound on workgroups with partials
+constexpr int NWG_MAX = 2048;     // upper bound on partial sums of one reduction
 constexpr size_t ALIGN = 256;
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -250,8 +250,8 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
     f.resid_parts = w.sparts;
     int nwg = launch_fused(f, NWG_MAX, s);
     launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, w.Lacc, s);
-    launch_reduce_parts<double>(w.gparts, 4 * nwg, (int64_t)R * R, (int64_t)R * R, w.GV, s);
-    nres = 4 * nwg;
+    launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, (int64_t)R * R, (int64_t)R * R, w.GV, s);
+    nres = FUSED_WAVES * nwg;
   } else {
     VpassArgs a{};
     a.X = X; a.x_dtype = xdt; a.v = v;
@@ -799,7 +799,7 @@ extern "C" int als_sweep_kernel(const void* A, int32_t a_dtype, int32_t N, const
     int nwg = launch_fused(f, NWG_MAX, s);
     if (reduce) {
       launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Lacc, s);
-      launch_reduce_parts<double>(w.gparts, 4 * nwg, (int64_t)R * R, (int64_t)R * R, GV, s);
+      launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, (int64_t)R * R, (int64_t)R * R, GV, s);
     }
   } else {
     VpassArgs a{};

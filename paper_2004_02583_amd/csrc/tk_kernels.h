@@ -87,15 +87,16 @@ struct FusedArgs {
   const float* Lq;       // I x R, quantised L~ (compute type float)
   const float* Lr;       // I x R, factor for the explicit residual (or null)
   float* lacc_parts;     // [nwg][I][R]
-  double* gv_parts;      // [nwg][R][R]
-  double* resid_parts;   // [nwg] (only when Lr != null)
+  double* gv_parts;      // [FUSED_WAVES * nwg][R][R]
+  double* resid_parts;   // [FUSED_WAVES * nwg] (only when Lr != null)
   int sketch; uint64_t seed; int mode;  // init variant: V = sketch, no G_V
   double* norm2_parts;   // [nwg] (init variant)
 };
 // Shapes the fused kernel takes (LDS budget), for the given residual mode.
 bool fused_supported(int x_dtype, const View& v, int R, int resid_mode);
 // Launches and returns the number of workgroups W; L_acc partials are
-// [W][I][R], Gram and residual partials [4W] (one per wave).
+// [W][I][R], Gram and residual partials [FUSED_WAVES * W] (one per wave).
+constexpr int FUSED_WAVES = 8;
 int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
 
 }  // namespace tk
