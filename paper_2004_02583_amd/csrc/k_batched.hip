@@ -1,0 +1,459 @@
+// Batched st-HOSVD-ALS (Algorithm 3.5) for many small order-3 FP32 tensors
+// in one persistent launch.  Each workgroup pulls tensor indices from a
+// device work queue and runs the whole decomposition of that tensor:
+// per mode the Section 5 initial sketch, the ALS loop of Algorithm 3.3 with
+// the stop test of eq. E5.01 evaluated on the device, FP64 Grams /
+// Cholesky / solves, the reduced QR (CholeskyQR2) and the mode-n TTM
+// truncation.  Fibres are streamed in tiles of TJ from the strided mode
+// view (no unfolding).  Every reduction has a fixed order.
+#include <math.h>
+
+#include "tk_kernels.h"
+
+namespace tk {
+
+namespace {
+
+constexpr int BR_MAX = 16;    // largest rank in a batch
+constexpr int BI_MAX = 128;   // largest mode size in a batch
+constexpr int GV_MAX = BR_MAX * BR_MAX;
+
+// Per-workgroup scratch slot (global memory): FP64 I x R matrices and the
+// two ping-pong buffers of the truncated tensor.
+struct Slot {
+  double *L, *Lnext, *Lacc, *Q1;
+  float *B0, *B1;
+};
+
+__device__ inline Slot slot_of(char* base, int64_t slot_bytes, int64_t belems) {
+  char* p = base + (int64_t)blockIdx.x * slot_bytes;
+  Slot s;
+  const int64_t m = BI_MAX * BR_MAX;
+  s.L = (double*)p;
+  s.Lnext = s.L + m;
+  s.Lacc = s.Lnext + m;
+  s.Q1 = s.Lacc + m;
+  s.B0 = (float*)(s.Q1 + m);
+  s.B1 = s.B0 + belems;
+  return s;
+}
+
+template <int NTH>
+__device__ double blk_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NTH / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// G = X^T X (r x r) of an m x r FP64 matrix (row-major), into LDS.
+template <int NTH>
+__device__ void blk_gram(const double* X, int m, int r, double* G) {
+  const int np = r * (r + 1) / 2;
+  for (int t = threadIdx.x; t < np; t += NTH) {
+    int a = 0, rem = t;
+    while (rem >= r - a) { rem -= r - a; ++a; }
+    const int b = a + rem;
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += X[i * r + a] * X[i * r + b];
+    G[a * r + b] = s;
+    G[b * r + a] = s;
+  }
+  __syncthreads();
+}
+
+// In-place lower Cholesky of the r x r LDS matrix G (one thread; r <= 16)
+// with the pivot test of Remark 3 (squared pivot <= PIVOT_TOL * max diag).
+template <int NTH>
+__device__ bool blk_chol(double* G, int r, int* bad) {
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int k = 0; k < r; ++k) mx = fmax(mx, G[k * r + k]);
+    int fail = !(mx > 0.0) || !isfinite(mx);
+    for (int k = 0; k < r && !fail; ++k) {
+      double d = G[k * r + k];
+      for (int l = 0; l < k; ++l) d -= G[k * r + l] * G[k * r + l];
+      if (!(d > PIVOT_TOL * mx) || !isfinite(d)) { fail = 1; break; }
+      d = sqrt(d);
+      G[k * r + k] = d;
+      for (int i = k + 1; i < r; ++i) {
+        double s = G[i * r + k];
+        for (int l = 0; l < k; ++l) s -= G[i * r + l] * G[k * r + l];
+        G[i * r + k] = s / d;
+      }
+    }
+    for (int i = 0; i < r; ++i)
+      for (int j = i + 1; j < r; ++j) G[i * r + j] = 0.0;
+    *bad = fail;
+  }
+  __syncthreads();
+  const bool f = *bad != 0;
+  __syncthreads();
+  return f;
+}
+
+// Row solves with a lower Cholesky factor C (LDS): gram = 1: X = B (C C^T)^-1,
+// gram = 0: X = B C^-T.  B, X: m x r FP64 (may alias: each row in place).
+template <int NTH>
+__device__ void blk_rsolve(const double* B, int m, int r, const double* C, int gram,
+                           double* X) {
+  for (int i = threadIdx.x; i < m; i += NTH) {
+    double y[BR_MAX];
+    for (int k = 0; k < r; ++k) y[k] = B[i * r + k];
+    for (int k = 0; k < r; ++k) {
+      double s = y[k];
+      for (int l = 0; l < k; ++l) s -= C[k * r + l] * y[l];
+      y[k] = s / C[k * r + k];
+    }
+    if (gram) {
+      for (int k = r - 1; k >= 0; --k) {
+        double s = y[k];
+        for (int l = k + 1; l < r; ++l) s -= C[l * r + k] * y[l];
+        y[k] = s / C[k * r + k];
+      }
+    }
+    for (int k = 0; k < r; ++k) X[i * r + k] = y[k];
+  }
+  __syncthreads();
+}
+
+// CholeskyQR2 of the FP64 m x r matrix L into Q (diag(R_hat) > 0).
+template <int NTH>
+__device__ bool blk_qr(const double* L, int m, int r, double* Q1, double* Q, double* G,
+                       int* bad) {
+  blk_gram<NTH>(L, m, r, G);
+  if (blk_chol<NTH>(G, r, bad)) return true;
+  blk_rsolve<NTH>(L, m, r, G, 0, Q1);
+  blk_gram<NTH>(Q1, m, r, G);
+  if (blk_chol<NTH>(G, r, bad)) return true;
+  blk_rsolve<NTH>(Q1, m, r, G, 0, Q);
+  return false;
+}
+
+// One pass over the fibres of the view [P, I, Q] of X (FP32) in tiles of TJ:
+//  kind 0 (sweep): V = X^T W (W = L~ in LDS, FP32), G_V += V^T V (FP64 in
+//                  registers of thread < r(r+1)/2), Lacc += X V;
+//  kind 1 (init):  V = rows of the Section 5 sketch, Lacc += X V;
+//  kind 2 (TTM):   V = X^T W (W = U in LDS), written to Y[p][r][q];
+//                  returns sum V^2 (FP64) for the next mode's norm.
+// Lacc (FP64, m x r, global) is overwritten.
+// Gram pairs (a <= b) of thread t are t and t + NTH (r(r+1)/2 <= 136).
+template <int NTH, int TJ>
+__device__ double blk_pass(int kind, const float* X, const View v, int r, const float* W,
+                           double* Lacc, double* gv, float* Y, uint64_t seed, int mode,
+                           float* Xt, float* Vt, int64_t* fb, double* red) {
+  constexpr int XS = TJ + 1;
+  const int I = (int)v.I;
+  const int64_t J = v.J();
+  // L-update accumulators: thread owns entries e = threadIdx.x + NTH k
+  constexpr int KMAX = BI_MAX * BR_MAX / NTH;
+  double lacc64[KMAX];
+  for (int k = 0; k < KMAX; ++k) lacc64[k] = 0.0;
+  const int np = r * (r + 1) / 2;
+  int ga[2] = {0, 0}, gb[2] = {0, 0};
+  for (int h = 0; h < 2; ++h) {
+    int rem = threadIdx.x + NTH * h, a = 0;
+    if (rem < np) {
+      while (rem >= r - a) { rem -= r - a; ++a; }
+      ga[h] = a;
+      gb[h] = a + rem;
+    }
+  }
+  double ssum = 0.0;
+  for (int64_t j0 = 0; j0 < J; j0 += TJ) {
+    if ((int)threadIdx.x < TJ) {
+      const int64_t j = j0 + threadIdx.x;
+      fb[threadIdx.x] = j < J ? v.fibre_base(j) : 0;
+    }
+    __syncthreads();
+    // X tile, coalesced along q (Q > 1) or along i (Q == 1)
+    for (int e = threadIdx.x; e < I * TJ; e += NTH) {
+      int ii, jj;
+      if (v.Q == 1) { ii = e % I; jj = e / I; }
+      else { jj = e % TJ; ii = e / TJ; }
+      const int64_t j = j0 + jj;
+      Xt[ii * XS + jj] = (j < J) ? X[fb[jj] + (int64_t)ii * v.Q] : 0.0f;
+    }
+    // V tile (TJ x r)
+    if (kind == 1) {
+      for (int e = threadIdx.x; e < TJ * r; e += NTH) {
+        const int jj = e / r, c = e % r;
+        const int64_t j = j0 + jj;
+        Vt[jj * BR_MAX + c] =
+            (j < J) ? sketch_value(seed, ((uint64_t)mode << 48) + (uint64_t)(j * r + c)) : 0.0f;
+      }
+    }
+    __syncthreads();
+    if (kind != 1) {
+      for (int e = threadIdx.x; e < TJ * r; e += NTH) {
+        const int jj = e % TJ, c = e / TJ;
+        float s = 0.0f;
+        for (int i = 0; i < I; ++i) s += W[i * BR_MAX + c] * Xt[i * XS + jj];
+        Vt[jj * BR_MAX + c] = s;
+      }
+      __syncthreads();
+    }
+    if (kind == 2) {
+      for (int e = threadIdx.x; e < TJ * r; e += NTH) {
+        const int jj = e % TJ, c = e / TJ;
+        const int64_t j = j0 + jj;
+        if (j < J) {
+          const int64_t p = j / v.Q, q = j - p * v.Q;
+          const float y = Vt[jj * BR_MAX + c];
+          Y[(p * r + c) * v.Q + q] = y;
+          ssum += (double)y * (double)y;
+        }
+      }
+    } else {
+      if (kind == 0) {
+        for (int h = 0; h < 2; ++h) {
+          if ((int)threadIdx.x + NTH * h < np) {
+            double s = 0.0;
+            for (int jj = 0; jj < TJ; ++jj)
+              s += (double)(Vt[jj * BR_MAX + ga[h]] * Vt[jj * BR_MAX + gb[h]]);
+            gv[h] += s;
+          }
+        }
+      }
+      for (int k = 0; k < KMAX; ++k) {
+        const int e = threadIdx.x + NTH * k;
+        if (e < I * r) {
+          const int i = e / r, c = e % r;
+          float s = 0.0f;
+          for (int jj = 0; jj < TJ; ++jj) s += Xt[i * XS + jj] * Vt[jj * BR_MAX + c];
+          lacc64[k] += (double)s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (kind != 2) {
+    for (int k = 0; k < KMAX; ++k) {
+      const int e = threadIdx.x + NTH * k;
+      if (e < I * r) Lacc[e] = lacc64[k];
+    }
+  }
+  __syncthreads();
+  return kind == 2 ? blk_sum<NTH>(ssum, red) : 0.0;
+}
+
+struct BatchDesc {
+  int64_t a_off, g_off, u_off[3];
+  int32_t dims[3], ranks[3];
+  int32_t orig;          // index of the tensor in the caller's arrays
+  int32_t pad;
+};
+
+struct BatchArgs {
+  const float* A;
+  const BatchDesc* desc;
+  int count;
+  float* U;
+  float* G;
+  int32_t* status;     // [count]
+  int32_t* iters;      // [3 * count]
+  int* queue;          // work counter
+  char* scratch;
+  int64_t slot_bytes, belems;
+  double tol;
+  int max_iters;
+  uint64_t seed;
+};
+
+template <int NTH, int TJ>
+__global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
+  constexpr int XS = TJ + 1;
+  __shared__ float Xt[BI_MAX * XS];
+  __shared__ float Vt[TJ * BR_MAX];
+  __shared__ float Wl[BI_MAX * BR_MAX];
+  __shared__ double G1[GV_MAX], G2[GV_MAX], GV[GV_MAX];
+  __shared__ double red[NTH];
+  __shared__ int64_t fb[TJ];
+  __shared__ int sh_t, sh_bad;
+  const Slot S = slot_of(a.scratch, a.slot_bytes, a.belems);
+
+  for (;;) {
+    if (threadIdx.x == 0) sh_t = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int t = sh_t;
+    __syncthreads();
+    if (t >= a.count) break;   // every wave of the workgroup leaves here
+    const BatchDesc d = a.desc[t];
+    int status = TK_OK;
+    int64_t cur[3] = {d.dims[0], d.dims[1], d.dims[2]};
+    const float* B = a.A + d.a_off;
+    // ||A||^2
+    double n2 = 0.0;
+    {
+      const int64_t n = cur[0] * cur[1] * cur[2];
+      double s = 0.0;
+      for (int64_t e = threadIdx.x; e < n; e += NTH) s += (double)B[e] * (double)B[e];
+      n2 = blk_sum<NTH>(s, red);
+    }
+    if (!isfinite(n2)) status = TK_ERR_NONFINITE;
+    const double normA = sqrt(n2);
+    double normB2 = n2;
+    for (int n = 0; n < 3 && status >= 0; ++n) {
+      View v;
+      v.P = 1;
+      for (int k = 0; k < n; ++k) v.P *= cur[k];
+      v.I = cur[n];
+      v.Q = 1;
+      for (int k = n + 1; k < 3; ++k) v.Q *= cur[k];
+      const int I = (int)v.I, r = d.ranks[n];
+      float* U = a.U + d.u_off[n];
+      int it = 0;
+      if (r == I) {
+        for (int e = threadIdx.x; e < I * I; e += NTH) Wl[(e / I) * BR_MAX + e % I] = (e / I == e % I);
+        for (int e = threadIdx.x; e < I * I; e += NTH) U[e] = (e / I == e % I) ? 1.0f : 0.0f;
+        __syncthreads();
+      } else {
+        // initial guess (Section 5): Y = B_(n) S, L0 = Q of its QR
+        double dummy[2] = {0.0, 0.0};
+        blk_pass<NTH, TJ>(1, B, v, r, nullptr, S.Lacc, dummy, nullptr, a.seed, n, Xt, Vt, fb,
+                          red);
+        if (blk_qr<NTH>(S.Lacc, I, r, S.Q1, S.L, G1, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
+        double res_prev = 0.0;
+        for (int k = 0;; ++k) {
+          // prep: L~ = L (L^T L)^{-1} in FP32, Gram of the rounded L~ (FP64)
+          blk_gram<NTH>(S.L, I, r, G1);
+          if (blk_chol<NTH>(G1, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
+          blk_rsolve<NTH>(S.L, I, r, G1, 1, S.Q1);
+          for (int e = threadIdx.x; e < I * r; e += NTH)
+            Wl[(e / r) * BR_MAX + e % r] = (float)S.Q1[e];
+          __syncthreads();
+          for (int e = threadIdx.x; e < r * (r + 1) / 2; e += NTH) {
+            int aa = 0, rem = e;
+            while (rem >= r - aa) { rem -= r - aa; ++aa; }
+            const int bb = aa + rem;
+            double s = 0.0;
+            for (int i = 0; i < I; ++i) s += (double)Wl[i * BR_MAX + aa] * (double)Wl[i * BR_MAX + bb];
+            G2[aa * r + bb] = s;
+            G2[bb * r + aa] = s;
+          }
+          __syncthreads();
+          if (blk_chol<NTH>(G2, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
+          // sweep: V = B_(n)^T L~ (tiles), G_V, Lacc = B_(n) V
+          double gv[2] = {0.0, 0.0};
+          blk_pass<NTH, TJ>(0, B, v, r, Wl, S.Lacc, gv, nullptr, 0, 0, Xt, Vt, fb, red);
+          {
+            const int np = r * (r + 1) / 2;
+            for (int h = 0; h < 2; ++h) {
+              if ((int)threadIdx.x + NTH * h < np) {
+                int aa = 0, rem = threadIdx.x + NTH * h;
+                while (rem >= r - aa) { rem -= r - aa; ++aa; }
+                const int bb = aa + rem;
+                GV[aa * r + bb] = gv[h];
+                GV[bb * r + aa] = gv[h];
+              }
+            }
+          }
+          __syncthreads();
+          if (blk_chol<NTH>(GV, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
+          blk_rsolve<NTH>(S.Lacc, I, r, GV, 1, S.Lnext);
+          // captured energy tr(Gq^{-1} G_V) = ||Cq^{-1} D||_F^2 (Cq = G2, D = GV)
+          double e = 0.0;
+          if ((int)threadIdx.x < r) {
+            const int col = threadIdx.x;
+            double z[BR_MAX];
+            for (int kk = 0; kk < r; ++kk) {
+              double s = (kk >= col) ? GV[kk * r + col] : 0.0;
+              for (int l = 0; l < kk; ++l) s -= G2[kk * r + l] * z[l];
+              z[kk] = s / G2[kk * r + kk];
+              e += z[kk] * z[kk];
+            }
+          }
+          e = blk_sum<NTH>(e, red);
+          const double res2 = normB2 - e;
+          const double res = sqrt(res2 > 0.0 ? res2 : 0.0);
+          it = k;
+          bool stop = false;
+          if (k >= 1 && fabs(res_prev - res) <= a.tol * normA) stop = true;
+          else if (k >= a.max_iters) { stop = true; status = TK_NOT_CONVERGED; }
+          if (stop) break;
+          for (int e2 = threadIdx.x; e2 < I * r; e2 += NTH) S.L[e2] = S.Lnext[e2];
+          __syncthreads();
+          res_prev = res;
+        }
+        if (status < 0) break;
+        // U = Q of the reduced QR of the returned L
+        if (blk_qr<NTH>(S.L, I, r, S.Q1, S.Lnext, G1, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
+        for (int e = threadIdx.x; e < I * r; e += NTH) {
+          const float u = (float)S.Lnext[e];
+          U[e] = u;
+          Wl[(e / r) * BR_MAX + e % r] = u;
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.iters[3 * d.orig + n] = it;
+      // B <- B x_n U^T (the last one lands in G)
+      float* dst = (n == 2) ? a.G + d.g_off : ((n == 0) ? S.B0 : S.B1);
+      double dummy[2] = {0.0, 0.0};
+      normB2 = blk_pass<NTH, TJ>(2, B, v, r, Wl, nullptr, dummy, dst, 0, 0, Xt, Vt, fb, red);
+      cur[n] = r;
+      B = dst;
+    }
+    if (threadIdx.x == 0) a.status[d.orig] = status;
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_int(int* p, int n, int val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+}  // namespace
+
+int batched_slot_bytes(int64_t belems) {
+  const int64_t m = BI_MAX * BR_MAX;
+  return (int)(4 * m * 8 + 2 * belems * 4 + 256);
+}
+
+bool batched_shape_ok(const int32_t* dims, const int32_t* ranks) {
+  for (int n = 0; n < 3; ++n)
+    if (dims[n] > BI_MAX || ranks[n] > BR_MAX) return false;
+  return true;
+}
+
+// Enqueues the queue reset and the persistent kernel on `s` (capturable:
+// no memset nodes).  cfg selects the tile shape: 0 (256 threads, TJ 64),
+// 1 (256, 32), 2 (128, 32), 3 (128, 64).
+void launch_batched(const BatchLaunch& L, int cfg, hipStream_t s) {
+  BatchArgs a;
+  a.A = L.A; a.desc = (const BatchDesc*)L.desc; a.count = L.count;
+  a.U = L.U; a.G = L.G; a.status = L.status; a.iters = L.iters; a.queue = L.queue;
+  a.scratch = L.scratch; a.slot_bytes = L.slot_bytes; a.belems = L.belems;
+  a.tol = L.tol; a.max_iters = L.max_iters; a.seed = L.seed;
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, L.queue, 1, 0);
+  const dim3 grid(L.nwg);
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_batched<256, 64>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_batched<256, 32>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_batched<128, 32>), grid, dim3(128), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_batched<128, 64>), grid, dim3(128), 0, s, a); break;
+  }
+}
+
+size_t batched_desc_bytes() { return sizeof(BatchDesc); }
+
+void fill_desc(void* host_desc, int t, int orig, int64_t a_off, int64_t g_off,
+               const int64_t* u_off, const int64_t* dims, const int32_t* ranks) {
+  BatchDesc* d = (BatchDesc*)host_desc + t;
+  d->orig = orig;
+  d->pad = 0;
+  d->a_off = a_off;
+  d->g_off = g_off;
+  for (int n = 0; n < 3; ++n) {
+    d->u_off[n] = u_off[n];
+    d->dims[n] = (int32_t)dims[n];
+    d->ranks[n] = ranks[n];
+  }
+}
+
+}  // namespace tk

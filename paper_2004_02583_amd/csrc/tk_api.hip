@@ -7,6 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "tk_kernels.h"
@@ -720,18 +723,139 @@ int qr_f64(const void* L, int64_t m, int32_t r, void* Q, void* Rhat, void* ws, s
 
 }  // extern "C"
 
+namespace tk {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batched st-HOSVD-ALS: persistent launch captured in a HIP graph.
+
+constexpr int BATCH_WG_PER_CU = 2;
+constexpr int BATCH_CUS = 256;
+
+struct BatchPlan {
+  bool persistent;
+  int64_t belems;
+  int nwg;
+  size_t desc_bytes, slot_bytes, total;
+};
+
+BatchPlan plan_batch(int count, const int64_t* dims3, const int32_t* ranks3) {
+  BatchPlan p{};
+  p.persistent = true;
+  int64_t be = 1;
+  size_t seq = 0;
+  for (int t = 0; t < count; ++t) {
+    const int64_t* d = dims3 + 3 * t;
+    const int32_t* r = ranks3 + 3 * t;
+    int32_t d32[3] = {(int32_t)d[0], (int32_t)d[1], (int32_t)d[2]};
+    if (d[0] > 128 || d[1] > 128 || d[2] > 128 || !batched_shape_ok(d32, r)) p.persistent = false;
+    be = std::max(be, (int64_t)r[0] * d[1] * d[2]);
+    be = std::max(be, (int64_t)r[0] * r[1] * d[2]);
+    seq = std::max(seq, driver_ws(1, TK_F32, 3, d, r));
+  }
+  p.belems = be;
+  p.nwg = std::min(count, BATCH_WG_PER_CU * BATCH_CUS);
+  p.desc_bytes = align_up(batched_desc_bytes() * count);
+  p.slot_bytes = align_up(batched_slot_bytes(be));
+  if (p.persistent)
+    p.total = p.desc_bytes + align_up(4 * (size_t)count) + align_up(12 * (size_t)count) + 256 +
+              p.slot_bytes * p.nwg;
+  else
+    p.total = seq;
+  return p;
+}
+
+// Autotuned tile shape per (count bucket, largest mode size, largest rank),
+// kept for the process and, when TK_AUTOTUNE_CACHE names a file, in that
+// file as "key cfg" lines.
+std::map<std::string, int>& tune_cache() {
+  static std::map<std::string, int> m;
+  return m;
+}
+std::mutex& tune_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
+std::string tune_key(int count, const int64_t* dims3, const int32_t* ranks3) {
+  int64_t mi = 0;
+  int mr = 0, cb = 1;
+  for (int t = 0; t < 3 * count; ++t) {
+    mi = std::max(mi, dims3[t]);
+    mr = std::max(mr, (int)ranks3[t]);
+  }
+  while (cb < count) cb <<= 1;
+  char buf[128];
+  snprintf(buf, sizeof buf, "gfx950/batched/n%d/i%lld/r%d", cb, (long long)mi, mr);
+  return buf;
+}
+
+int tune_lookup(const std::string& key) {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  auto& m = tune_cache();
+  auto it = m.find(key);
+  if (it != m.end()) return it->second;
+  const char* path = getenv("TK_AUTOTUNE_CACHE");
+  if (path) {
+    if (FILE* f = fopen(path, "r")) {
+      char k[256];
+      int c;
+      while (fscanf(f, "%255s %d", k, &c) == 2) m[k] = c;
+      fclose(f);
+    }
+    it = m.find(key);
+    if (it != m.end()) return it->second;
+  }
+  return -1;
+}
+
+void tune_store(const std::string& key, int cfg) {
+  std::lock_guard<std::mutex> g(tune_mutex());
+  tune_cache()[key] = cfg;
+  if (const char* path = getenv("TK_AUTOTUNE_CACHE")) {
+    if (FILE* f = fopen(path, "a")) {
+      fprintf(f, "%s %d\n", key.c_str(), cfg);
+      fclose(f);
+    }
+  }
+}
+
+// Times every tile shape on the batch itself (second of two runs each).
+int autotune_batched(const BatchLaunch& L, hipStream_t s, int* best_out) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bc = 0;
+  for (int cfg = 0; cfg < BATCHED_CONFIGS; ++cfg) {
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPCHK(hipEventRecord(e0, s));
+      launch_batched(L, cfg, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (ms < best) { best = ms; bc = cfg; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *best_out = bc;
+  return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
 extern "C" {
 
 size_t als_sthosvd_batched_workspace_bytes(int32_t count, const int64_t* dims3,
                                            const int32_t* ranks3) {
   if (count < 1 || !dims3 || !ranks3) return 0;
-  size_t mx = 0;
-  for (int t = 0; t < count; ++t) {
+  for (int t = 0; t < count; ++t)
     if (!valid_dims(3, dims3 + 3 * t) || !valid_ranks(3, dims3 + 3 * t, ranks3 + 3 * t))
       return 0;
-    mx = std::max(mx, driver_ws(1, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t));
-  }
-  return mx;
+  return plan_batch(count, dims3, ranks3).total;
 }
 
 int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t count,
@@ -749,24 +873,93 @@ int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t count,
   Opts o;
   int rc = read_opts(opts, 3, o);
   if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const BatchPlan plan = plan_batch(count, dims3, ranks3);
   int worst = TK_OK;
+  if (!plan.persistent) {
+    // shapes beyond the persistent kernel's limits: one tensor at a time
+    for (int t = 0; t < count; ++t) {
+      const float* A = (const float*)A_packed + a_off[t];
+      void* U[3];
+      for (int n = 0; n < 3; ++n) U[n] = (float*)U_packed + u_off[3 * t + n];
+      void* G = (float*)G_packed + g_off[t];
+      tk_als_info info;
+      tk_als_opts o2;
+      memset(&o2, 0, sizeof(o2));
+      o2.struct_size = sizeof(o2);
+      o2.tol = o.tol; o2.max_iters = o.max_iters; o2.resid_mode = o.resid_mode; o2.seed = o.seed;
+      rc = run_driver(1, A, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t, &o2, U, G, ws, ws_bytes,
+                      &info, stream);
+      if (status) status[t] = rc;
+      if (iters)
+        for (int n = 0; n < 3; ++n) iters[3 * t + n] = info.iters[n];
+      if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
+      else if (rc > 0 && worst == TK_OK) worst = rc;
+    }
+    return worst;
+  }
+  // descriptor table, largest tensors first (the work queue then balances)
+  std::vector<int> ord(count);
+  for (int t = 0; t < count; ++t) ord[t] = t;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    return dims3[3 * x] * dims3[3 * x + 1] * dims3[3 * x + 2] >
+           dims3[3 * y] * dims3[3 * y + 1] * dims3[3 * y + 2];
+  });
+  std::vector<char> hdesc(plan.desc_bytes);
+  for (int k = 0; k < count; ++k) {
+    const int t = ord[k];
+    fill_desc(hdesc.data(), k, t, a_off[t], g_off[t], u_off + 3 * t, dims3 + 3 * t,
+              ranks3 + 3 * t);
+  }
+  Arena ar(ws, ws_bytes);
+  void* ddesc = ar.take(plan.desc_bytes);
+  int32_t* dstatus = (int32_t*)ar.take(4 * (size_t)count);
+  int32_t* diters = (int32_t*)ar.take(12 * (size_t)count);
+  int* queue = (int*)ar.take(256);
+  char* scratch = (char*)ar.take(plan.slot_bytes * plan.nwg);
+  HIPCHK(hipMemcpyAsync(ddesc, hdesc.data(), batched_desc_bytes() * count,
+                        hipMemcpyHostToDevice, s));
+  BatchLaunch L{};
+  L.A = (const float*)A_packed; L.desc = ddesc; L.count = count;
+  L.U = (float*)U_packed; L.G = (float*)G_packed;
+  L.status = dstatus; L.iters = diters; L.queue = queue;
+  L.scratch = scratch; L.slot_bytes = (int64_t)plan.slot_bytes; L.belems = plan.belems;
+  L.tol = o.tol; L.max_iters = o.max_iters; L.seed = o.seed; L.nwg = plan.nwg;
+  const std::string key = tune_key(count, dims3, ranks3);
+  int cfg = tune_lookup(key);
+  if (cfg < 0) {
+    rc = autotune_batched(L, s, &cfg);
+    if (rc) return rc;
+    tune_store(key, cfg);
+  }
+  // capture queue reset + persistent kernel in a graph on a private stream,
+  // replay it on the caller's stream
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    launch_batched(L, cfg, cs);
+    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+  }
+  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  hipStreamDestroy(cs);
+  if (!ok) return TK_ERR_HIP;
+  std::vector<int32_t> hs(count), hi(3 * (size_t)count);
+  HIPCHK(hipMemcpy(hs.data(), dstatus, 4 * (size_t)count, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(hi.data(), diters, 12 * (size_t)count, hipMemcpyDeviceToHost));
   for (int t = 0; t < count; ++t) {
-    const float* A = (const float*)A_packed + a_off[t];
-    void* U[3];
-    for (int n = 0; n < 3; ++n) U[n] = (float*)U_packed + u_off[3 * t + n];
-    void* G = (float*)G_packed + g_off[t];
-    tk_als_info info;
-    tk_als_opts o2;
-    memset(&o2, 0, sizeof(o2));
-    o2.struct_size = sizeof(o2);
-    o2.tol = o.tol; o2.max_iters = o.max_iters; o2.resid_mode = o.resid_mode; o2.seed = o.seed;
-    rc = run_driver(1, A, TK_F32, 3, dims3 + 3 * t, ranks3 + 3 * t, &o2, U, G, ws, ws_bytes,
-                    &info, stream);
-    if (status) status[t] = rc;
+    if (status) status[t] = hs[t];
     if (iters)
-      for (int n = 0; n < 3; ++n) iters[3 * t + n] = info.iters[n];
-    if (rc < 0 && (worst >= 0 || rc < worst)) worst = rc;
-    else if (rc > 0 && worst == TK_OK) worst = rc;
+      for (int n = 0; n < 3; ++n) iters[3 * t + n] = hi[3 * t + n];
+    const int rc2 = hs[t];
+    if (rc2 < 0 && (worst >= 0 || rc2 < worst)) worst = rc2;
+    else if (rc2 > 0 && worst == TK_OK) worst = rc2;
   }
   return worst;
 }

@@ -99,4 +99,22 @@ bool fused_supported(int x_dtype, const View& v, int R, int resid_mode);
 constexpr int FUSED_WAVES = 8;
 int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
 
+// Batched st-HOSVD-ALS of small order-3 FP32 tensors (I_n <= 128,
+// R_n <= 16): one persistent launch, one tensor per workgroup at a time.
+struct BatchLaunch {
+  const float* A; const void* desc; int count;
+  float* U; float* G;
+  int32_t* status; int32_t* iters; int* queue;
+  char* scratch; int64_t slot_bytes, belems;
+  double tol; int max_iters; uint64_t seed;
+  int nwg;
+};
+constexpr int BATCHED_CONFIGS = 4;
+int batched_slot_bytes(int64_t belems);
+bool batched_shape_ok(const int32_t* dims, const int32_t* ranks);
+void launch_batched(const BatchLaunch& L, int cfg, hipStream_t s);
+size_t batched_desc_bytes();
+void fill_desc(void* host_desc, int t, int orig, int64_t a_off, int64_t g_off,
+               const int64_t* u_off, const int64_t* dims, const int32_t* ranks);
+
 }  // namespace tk
