@@ -28,6 +28,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_sweep_mode1_200x4_f32_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_02583_amd", "csrc", "k_fused.hip")
 DIMS = (200, 200, 200, 200)
 RANK = 20
 TOL = 1e-4
@@ -38,20 +40,17 @@ def log(msg):
 
 
 def step_bytes(dims, ranks, iters, elem=4):
-    """Algorithmic HBM bytes of one st-HOSVD-ALS call in natural order: the
-    norm of A, then per mode n on the current tensor B (s bytes): the norm of
-    B (n > 0), the initial sketch pass, iters+1 sweeps, and the truncation
-    (read s, write s*R_n/I_n)."""
+    """Algorithmic HBM bytes of one st-HOSVD-ALS call in natural order: per
+    mode n on the current tensor B (s bytes): the initial sketch pass (which
+    also yields ||B||), iters+1 sweeps, and the truncation (read s, write
+    s*R_n/I_n)."""
     cur = list(dims)
     total = 0.0
     size = float(elem)
     for d in cur:
         size *= d
-    total += size                      # ||A||
     for n in range(len(dims)):
-        if n > 0:
-            total += size              # ||B||
-        total += size                  # sketch pass
+        total += size                  # sketch pass (+ norm)
         total += (iters[n] + 1) * size  # sweeps
         nxt = size * ranks[n] / cur[n]
         total += size + nxt            # TTM read + write
@@ -87,7 +86,40 @@ def time_sweep_kernel(tk, A, Lq, launches=10):
     return start.elapsed_time(stop) / launches
 
 
-def cpu_baseline(A, ncols=2_000_000, sweeps=3):
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused sweep (mode 1) from the committed
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
+    None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters (read nbytes, write nbytes)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {nbytes} bytes")
+
+
+def cpu_baseline(A, ncols=8_000_000, sweeps=3):
     """Literal Algorithm 3.3 sweeps of the FP64 oracle on the first ``ncols``
     columns of the mode-1 unfolding (a 200 x ncols sample)."""
     import numpy as np
@@ -113,6 +145,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not "
@@ -125,6 +159,8 @@ def main():
 
     tk.load_library()
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration()
     log("generating 200^4 FP32 workload on the GPU")
     w = synth.workload_4way_torch(DIMS, RANK, 1e-4, device=dev)
     A = w["A"]
@@ -204,7 +240,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_fused (ALS sweep, mode 1, FP32)",
+                     "traffic": measured_traffic(), "kernel": "k_fused (ALS sweep, mode 1, FP32)",
                      "kernel_ms": round(k_ms, 4), "bytes_per_launch": sweep_bytes},
         "cpu_baseline": cpu,
         "iters": iters,

@@ -7,7 +7,9 @@
 //    G_V  += v_j v_j^T               (R_k^T R_k, FP32 per tile, FP64 across)
 //    L_acc += a_j v_j^T              (A_(n) R_k, per-workgroup partial)
 // and optionally the explicit residual sum_j ||a_j - L v_j||^2.  The init
-// variant replaces v_j by row j of the Section 5 sketch S.
+// variant replaces v_j by row j of the Section 5 sketch S (and can add up
+// ||A||^2 on the way); the TTM variant keeps only v_j = U^T a_j, which is
+// fibre j of B x_n U^T, and writes it out.
 //
 // Work layout: a workgroup of 8 waves (two per SIMD) walks 64-fibre tiles
 // (persistent grid, tile = blockIdx + k * gridDim).  The tile X (I x 64) is
@@ -64,7 +66,8 @@ __host__ __device__ inline Lds lds_layout(int I, int NR, int mode) {
   l.lq = l.xs + (xrows + 1) * XLD;            // + spare row for the stash
   l.lr = l.lq + (mode != 2 ? xrows * RS : 0);
   l.vf = l.lr + (mode == 1 ? xrows * (RP + 1) : 0);
-  l.total = l.vf + TJ * RS;
+  // TTM keeps V transposed ([RP][TJ + 1]) for coalesced, conflict-free writes
+  l.total = l.vf + (mode == 3 && RP * (TJ + 1) > TJ * RS ? RP * (TJ + 1) : TJ * RS);
   return l;
 }
 
@@ -105,16 +108,19 @@ __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v,
 }
 
 // Rows past I go to the spare row `xrows` of the X tile (no branches).
-template <typename T, int LAYOUT, int IC>
+// With NORM the squares of the tile's elements are added to nsum (FP64).
+template <typename T, int LAYOUT, int IC, bool NORM>
 __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w, const T* pf,
-                                      bool ok, int xrows, float* Xs) {
+                                      bool ok, int xrows, float* Xs, double& nsum) {
   const int I = (int)v.I;
   if (LAYOUT == 0) {
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
       const int ii = NW * k + w;
       const int row = ii < I ? ii : xrows;
-      Xs[row * XLD + lane] = ok ? to_f<T>(pf[k]) : 0.0f;
+      const float x = ok ? to_f<T>(pf[k]) : 0.0f;
+      Xs[row * XLD + lane] = x;
+      if (NORM && ii < I) nsum += (double)x * (double)x;
     }
   } else {
     const int64_t J = v.J();
@@ -125,12 +131,15 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
       const bool fok = j0 + w + NW * f < J;
       const int ii = lane + 64 * c;
       const int row = ii < I ? ii : xrows;
-      Xs[row * XLD + w + NW * f] = fok ? to_f<T>(pf[k]) : 0.0f;
+      const float x = fok ? to_f<T>(pf[k]) : 0.0f;
+      Xs[row * XLD + w + NW * f] = x;
+      if (NORM && ii < I) nsum += (double)x * (double)x;
     }
   }
 }
 
-// MODE 0: sweep; 1: sweep + explicit residual; 2: init (sketch, no Gram).
+// MODE 0: sweep; 1: sweep + explicit residual; 2: init (sketch, no Gram);
+// 3: TTM (R-update only, V written to Y).
 template <typename T, int NR, int MODE, int LAYOUT, int IC>
 __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   extern __shared__ float smem[];
@@ -159,9 +168,10 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   // ---- once per kernel: zero the X tile (rows >= I stay zero), load Lq/Lr
   for (int e = threadIdx.x; e < (xrows + 1) * XLD; e += NT) Xs[e] = 0.0f;
   if (MODE != 2) {
+    const int64_t ldi = a.lq_ldi ? a.lq_ldi : R, ldo = a.lq_ldi ? a.lq_ldo : 1;
     for (int e = threadIdx.x; e < xrows * RP; e += NT) {
       const int i = e / RP, r = e % RP;
-      Lq[i * RS + r] = (i < I && r < R) ? a.Lq[i * R + r] : 0.0f;
+      Lq[i * RS + r] = (i < I && r < R) ? a.Lq[i * ldi + r * ldo] : 0.0f;
     }
   }
   if (MODE == 1) {
@@ -187,6 +197,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     gd[p][0] = gd[p][1] = gd[p][2] = gd[p][3] = 0.0;
   }
   double rsum = 0.0;
+  const bool want_norm = MODE == 2 && a.norm2_parts != nullptr;
 
   const T* X = (const T*)a.X;
   const int64_t ntiles = ceil_div(J, TJ);
@@ -199,7 +210,8 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   for (; tile < ntiles; tile += nwg) {
     const int64_t j0 = tile * TJ;
     __syncthreads();
-    stash<T, LAYOUT, IC>(v, j0, lane, w, pf, pf_ok, xrows, Xs);
+    if (MODE == 2 && want_norm) stash<T, LAYOUT, IC, true>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
+    else stash<T, LAYOUT, IC, false>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
     __syncthreads();
     if (tile + nwg < ntiles) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
 
@@ -234,8 +246,13 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
             for (int q = 0; q < 4; ++q) { ac[q] = an[q]; bc[q] = bn[q]; }
           }
           // V[16 fb + 4 lk + q][16 n + lr] = vacc[q]
+          if (MODE == 3) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) Vf[(16 * fb + 4 * lk + q) * RS + 16 * n + lr] = vacc[q];
+            for (int q = 0; q < 4; ++q) Vf[(16 * n + lr) * (TJ + 1) + 16 * fb + 4 * lk + q] = vacc[q];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Vf[(16 * fb + 4 * lk + q) * RS + 16 * n + lr] = vacc[q];
+          }
         }
       }
     } else {
@@ -250,6 +267,27 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
       }
     }
     __syncthreads();
+
+    if (MODE == 3) {
+      // fibre j of Y = B x_n U^T: Y[p, r, q] = V[j, r], coalesced along q
+      float* Y = a.y;
+      if (LAYOUT == 0) {
+        const int64_t j = j0 + lane;
+        if (j < J) {
+          const int64_t p = j / v.Q, q = j - p * v.Q;
+          float* yb = Y + p * (int64_t)R * v.Q + q;
+          for (int r = w; r < R; r += NW) {
+            yb[(int64_t)r * v.Q] = Vf[r * (TJ + 1) + lane];
+          }
+        }
+      } else {
+        for (int e = threadIdx.x; e < TJ * R; e += NT) {
+          const int jl = e / R, r = e - jl * R;
+          if (j0 + jl < J) Y[(j0 + jl) * R + r] = Vf[r * (TJ + 1) + jl];
+        }
+      }
+      continue;
+    }
 
     // L-update: tile (m, n) += X[16m.., f] V[f, 16n..] over the 64 fibres.
     {
@@ -328,6 +366,13 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 
   // ---- per-workgroup outputs
   const int wg = blockIdx.x;
+  if (MODE == 3) return;
+  if (want_norm) {
+    // sum of squares of the tensor (init), one per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off, 64);
+    if (lane == 0) a.norm2_parts[wg * NW + w] = rsum;
+  }
   float* lp = a.lacc_parts + (int64_t)wg * I * R;
 #pragma unroll
   for (int u = 0; u < U2; ++u) {
@@ -393,7 +438,8 @@ int launch_nr(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
   const size_t bytes = (size_t)lds_layout((int)a.v.I, NR, mode).total * 4;
   if (mode == 0) launch_mode<T, NR, 0>(a, nwg, bytes, s);
   else if (mode == 1) launch_mode<T, NR, 1>(a, nwg, bytes, s);
-  else launch_mode<T, NR, 2>(a, nwg, bytes, s);
+  else if (mode == 2) launch_mode<T, NR, 2>(a, nwg, bytes, s);
+  else launch_mode<T, NR, 3>(a, nwg, bytes, s);
   return nwg;
 }
 
@@ -419,6 +465,13 @@ bool fused_supported(int x_dtype, const View& v, int R, int resid_mode) {
   return (size_t)lds_layout((int)v.I, NR, mode).total * 4 <= (size_t)LDS_MAX_BYTES;
 }
 
+bool fused_ttm_supported(int x_dtype, const View& v, int64_t J) {
+  if (x_dtype != TK_F32 && x_dtype != TK_BF16) return false;
+  if (v.I > 256 || v.I < 1 || J < 1 || J > 48) return false;
+  const int NR = (int)((J + 15) / 16);
+  return (size_t)lds_layout((int)v.I, NR, 3).total * 4 <= (size_t)LDS_MAX_BYTES;
+}
+
 int fused_workgroups(const View& v) {
   int64_t ntiles = ceil_div(v.J(), TJ);
   return (int)(ntiles < NWG ? ntiles : NWG);
@@ -427,7 +480,7 @@ int fused_workgroups(const View& v) {
 int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s) {
   int nwg = fused_workgroups(a.v);
   if (nwg > nwg_max / NW) nwg = nwg_max / NW;
-  const int mode = a.sketch ? 2 : (a.Lr ? 1 : 0);
+  const int mode = a.y ? 3 : a.sketch ? 2 : (a.Lr ? 1 : 0);
   if (a.x_dtype == TK_F32) return launch_t<float>(a, mode, nwg, s);
   return launch_t<bf16_t>(a, mode, nwg, s);
 }

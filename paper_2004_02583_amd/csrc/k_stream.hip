@@ -333,6 +333,10 @@ int lpass_chunks(const View& v, int64_t R, int nwg_max) {
   return (int)want;
 }
 
+int lpass_blocks(const View& v, int chunks) {
+  return (int)(chunks * ceil_div(v.I, TI));
+}
+
 void launch_lpass(const LpassArgs& a, int chunks, hipStream_t s) {
   int64_t ntiles = ceil_div(a.v.J(), TJ);
   int64_t tpc = ceil_div(ntiles, chunks);

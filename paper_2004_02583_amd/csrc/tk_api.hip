@@ -89,7 +89,7 @@ bool valid_dtype(int dt) { return dt == TK_F64 || dt == TK_F32 || dt == TK_BF16;
 // Device status block read back once per sweep.
 struct DevStatus {
   int status;
-  int pad;
+  int prep_status;   // failure of the speculative preparation of the next sweep
   double res2;
   double energy;
   double norm2;
@@ -102,6 +102,7 @@ struct ModeWs {
   void *Lq, *Lr;               // compute type
   void *parts;                 // lacc/Y partials (compute type)
   double *gparts, *sparts;     // Gram partials, scalar partials
+  double* rtmp;                // first-stage sums of the two-stage reductions
   void* V;                     // generic path: J x R (compute type)
   DevStatus* st;
 };
@@ -122,6 +123,7 @@ void carve_mode(Arena& ar, int xdt, const View& v, int R, ModeWs& w) {
   w.parts = ar.take((size_t)NWG_MAX * IR * cs);
   w.gparts = (double*)ar.take((size_t)NWG_MAX * R * R * 8);
   w.sparts = (double*)ar.take((size_t)NWG_MAX * 8 * 2);
+  w.rtmp = (double*)ar.take((size_t)(REDUCE_GROUPS / 4) * IR * 8);
   w.st = (DevStatus*)ar.take(sizeof(DevStatus));
   if (!fused_supported(xdt, v, R, TK_RESID_EXPLICIT)) w.V = ar.take((size_t)v.J() * R * cs);
   else w.V = nullptr;
@@ -165,15 +167,15 @@ int read_opts(const tk_als_opts* o, int N, Opts& out) {
 // ---------------------------------------------------------------------------
 // Small FP64 building blocks
 
-// Reduced QR (CholeskyQR2) of the FP64 m x r matrix L into Q (FP64).
-void qr_enqueue(const double* L, int64_t m, int r, double* Q, double* Q1, double* C1,
-                double* C2, int* status, hipStream_t s) {
-  launch_gram<double>(L, m, r, C1, s);
-  launch_chol(C1, r, status, s);
-  launch_row_solve<double>(L, m, r, C1, 0, Q1, nullptr, s);
-  launch_gram<double>(Q1, m, r, C2, s);
-  launch_chol(C2, r, status, s);
-  launch_row_solve<double>(Q1, m, r, C2, 0, Q, nullptr, s);
+// Reduced QR (CholeskyQR2) of the FP64 m x r matrix L into Q (FP64), one
+// workgroup; Q1 is m x r scratch.
+void qr_enqueue(const double* L, int64_t m, int r, double* Q, double* Q1, int* status,
+                hipStream_t s) {
+  StepArgs a{};
+  a.m = m; a.r = r; a.ops = STEP_QR;
+  a.Qin = L; a.Q1 = Q1; a.Qout = Q;
+  a.status = status;
+  launch_mode_step(a, TK_F64, s);
 }
 
 int read_status(const DevStatus* d, DevStatus* h, hipStream_t s) {
@@ -184,10 +186,10 @@ int read_status(const DevStatus* d, DevStatus* h, hipStream_t s) {
 
 // ||X||^2 in FP64 (deterministic two-stage reduction).
 int norm2_enqueue(const void* X, int xdt, int64_t n, double* sparts, double* out,
-                  hipStream_t s) {
+                  double* rtmp, hipStream_t s) {
   int chunks = (int)std::min<int64_t>(NWG_MAX, std::max<int64_t>(1, ceil_div(n, 65536)));
   launch_norm2_parts(X, xdt, n, chunks, sparts, s);
-  launch_reduce_parts<double>(sparts, chunks, 1, 1, out, s);
+  launch_reduce_parts<double>(sparts, chunks, 1, 1, out, rtmp, s);
   return TK_OK;
 }
 
@@ -196,52 +198,58 @@ struct ModeResult {
   double resid;
 };
 
-// Y (FP64, I x R) = B_(n) S  (Section 5 initial sketch), partial-reduced.
+// Y (FP64, I x R) = B_(n) S  (Section 5 initial sketch), partial-reduced;
+// with norm2 != null the same pass also yields ||B||_F^2.
 void init_enqueue(const void* X, int xdt, const View& v, int R, uint64_t seed, int mode,
-                  ModeWs& w, double* Yout, hipStream_t s) {
+                  ModeWs& w, double* Yout, double* norm2, hipStream_t s) {
   const int64_t IR = v.I * (int64_t)R;
   if (fused_supported(xdt, v, R, TK_RESID_TRACE)) {
     FusedArgs f{};
     f.X = X; f.x_dtype = xdt; f.v = v; f.R = R;
     f.lacc_parts = (float*)w.parts;
     f.sketch = 1; f.seed = seed; f.mode = mode;
+    f.norm2_parts = norm2 ? w.sparts : nullptr;
     int nwg = launch_fused(f, NWG_MAX, s);
-    launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Yout, s);
+    launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Yout, w.rtmp, s);
+    if (norm2) launch_reduce_parts<double>(w.sparts, FUSED_WAVES * nwg, 1, 1, norm2, w.rtmp, s);
   } else {
     LpassArgs a{};
     a.X = X; a.x_dtype = xdt; a.v = v; a.v_kind = 1; a.R = R; a.seed = seed; a.mode = mode;
     a.parts = w.parts;
+    a.norm2_parts = norm2 ? w.sparts : nullptr;
     int chunks = lpass_chunks(v, R, NWG_MAX);
     launch_lpass(a, chunks, s);
     if (cdtype(xdt) == TK_F64)
-      launch_reduce_parts<double>((const double*)w.parts, chunks, IR, IR, Yout, s);
+      launch_reduce_parts<double>((const double*)w.parts, chunks, IR, IR, Yout, w.rtmp, s);
     else
-      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, Yout, s);
+      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, Yout, w.rtmp, s);
+    if (norm2)
+      launch_reduce_parts<double>(w.sparts, lpass_blocks(v, chunks), 1, 1, norm2, w.rtmp, s);
   }
 }
 
-// One sweep of Algorithm 3.3 from w.L: R-update (never stored when fused),
-// L-update into w.Lnext, residual into st->res2.
+// The step that follows the initial pass: L = Q of the reduced QR of Lacc,
+// then L~, its quantised Gram factor (and L for the explicit residual) for
+// the first sweep.
+void init_finish_enqueue(const View& v, int R, int xdt, int resid_mode, ModeWs& w,
+                         hipStream_t s) {
+  StepArgs a{};
+  a.m = v.I; a.r = R; a.ops = STEP_QR | STEP_PREP;
+  a.Qin = w.Lacc; a.Q1 = w.Q1; a.Qout = w.L;
+  a.Lq = w.Lq; a.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; a.Cq = w.Cq;
+  a.status = &w.st->status; a.prep_status = &w.st->prep_status;
+  launch_mode_step(a, cdtype(xdt), s);
+}
+
+// One sweep of Algorithm 3.3 from w.L, whose L~ (w.Lq), Gram factor (w.Cq)
+// and compute-type copy (w.Lr, explicit residual) are already prepared:
+// R-update (never stored when fused), L-update into w.Lnext, residual into
+// st->res2, and the speculative preparation of the sweep from w.Lnext.
 void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
                    int resid_mode, ModeWs& w, hipStream_t s) {
   const int64_t IR = v.I * (int64_t)R;
   const int cdt = cdtype(xdt);
-  // prep: L~ = L (L^T L)^{-1}, quantised; Gram of the quantised L~ (FP64).
-  launch_gram<double>(w.L, v.I, R, w.CL, s);
-  launch_chol(w.CL, R, &w.st->status, s);
-  if (cdt == TK_F64) {
-    launch_row_solve<double>(w.L, v.I, R, w.CL, 1, (double*)w.Lq, nullptr, s);
-    launch_gram<double>((const double*)w.Lq, v.I, R, w.Cq, s);
-  } else {
-    launch_row_solve<float>(w.L, v.I, R, w.CL, 1, (float*)w.Lq, nullptr, s);
-    launch_gram<float>((const float*)w.Lq, v.I, R, w.Cq, s);
-  }
-  launch_chol(w.Cq, R, &w.st->status, s);
   const bool expl = resid_mode == TK_RESID_EXPLICIT;
-  if (expl) {
-    if (cdt == TK_F64) launch_convert<double>(w.L, IR, (double*)w.Lr, s);
-    else launch_convert<float>(w.L, IR, (float*)w.Lr, s);
-  }
   int nres = 0;
   if (fused_supported(xdt, v, R, resid_mode)) {
     FusedArgs f{};
@@ -252,8 +260,9 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
     f.gv_parts = w.gparts;
     f.resid_parts = w.sparts;
     int nwg = launch_fused(f, NWG_MAX, s);
-    launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, w.Lacc, s);
-    launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, (int64_t)R * R, (int64_t)R * R, w.GV, s);
+    launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, w.Lacc, w.rtmp, s);
+    launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, (int64_t)R * R, (int64_t)R * R,
+                                w.GV, w.rtmp, s);
     nres = FUSED_WAVES * nwg;
   } else {
     VpassArgs a{};
@@ -265,52 +274,67 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
     launch_vpass(a, NWG_MAX, &nres, s);
     int gch = (int)std::min<int64_t>(NWG_MAX, std::max<int64_t>(1, ceil_div(v.J(), 4096)));
     launch_gram_parts(w.V, cdt, v.J(), R, gch, w.gparts, s);
-    launch_reduce_parts<double>(w.gparts, gch, (int64_t)R * R, (int64_t)R * R, w.GV, s);
+    launch_reduce_parts<double>(w.gparts, gch, (int64_t)R * R, (int64_t)R * R, w.GV, w.rtmp, s);
     LpassArgs l{};
     l.X = X; l.x_dtype = xdt; l.v = v; l.v_kind = 0; l.V = w.V; l.R = R;
     l.parts = w.parts;
     int chunks = lpass_chunks(v, R, NWG_MAX);
     launch_lpass(l, chunks, s);
     if (cdt == TK_F64)
-      launch_reduce_parts<double>((const double*)w.parts, chunks, IR, IR, w.Lacc, s);
+      launch_reduce_parts<double>((const double*)w.parts, chunks, IR, IR, w.Lacc, w.rtmp, s);
     else
-      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, w.Lacc, s);
+      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, w.Lacc, w.rtmp, s);
   }
-  double* rsum = nullptr;
+  StepArgs a{};
+  a.m = v.I; a.r = R; a.ops = STEP_SOLVE | STEP_PREP | STEP_PREP_SPECULATIVE;
+  a.Lacc = w.Lacc; a.GV = w.GV; a.Lnext = w.Lnext; a.norm2 = norm2;
   if (expl) {
-    launch_reduce_parts<double>(w.sparts, nres, 1, 1, &w.st->rsum, s);
-    rsum = &w.st->rsum;
+    launch_reduce_parts<double>(w.sparts, nres, 1, 1, &w.st->rsum, w.rtmp, s);
+    a.rsum = &w.st->rsum;
   }
-  // finish: L_{k+1} = L_acc G_V^{-1}; res^2 from the Grams (or explicit).
-  launch_chol(w.GV, R, &w.st->status, s);
-  launch_row_solve<double>(w.Lacc, v.I, R, w.GV, 1, w.Lnext, nullptr, s);
-  launch_trace_resid(w.Cq, w.GV, R, norm2, rsum, &w.st->res2, s);
+  a.res2 = &w.st->res2;
+  a.Lq = w.Lq; a.Lr = expl ? w.Lr : nullptr; a.Cq = w.Cq;
+  a.status = &w.st->status; a.prep_status = &w.st->prep_status;
+  launch_mode_step(a, cdt, s);
 }
 
 // Algorithm 3.3 on the mode view of X with rank R, initial guess of
 // Section 5, stop test E5.01 (first at k = 1, against norm_a = ||A||_F of the
-// input tensor); normb2 = ||X||_F^2 of the tensor being swept (trace form of
-// the residual).  On return U64 (FP64 I x R) holds Q of the reduced QR of
-// the returned L.
-int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, double normb2,
+// input tensor; norm_a < 0: the norm of X).  normx2 = ||X||_F^2 of the
+// tensor being swept (trace form of the residual); when it is negative on
+// entry the initial pass computes it and returns it there.  On return U64
+// (FP64 I x R) holds Q of the reduced QR of the returned L.
+int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, double& normx2,
                double norm_a, int mode, ModeWs& w, double* U64, ModeResult& mr,
                hipStream_t s) {
   mr.iters = 0; mr.converged = 1; mr.sweeps = 0; mr.resid = 0.0;
+  DevStatus h{};
+  const bool want_norm = normx2 < 0.0;
+  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
   if (R == v.I) {
+    if (want_norm) {
+      norm2_enqueue(X, xdt, v.P * v.I * v.Q, w.sparts, &w.st->norm2, w.rtmp, s);
+      int rc = read_status(w.st, &h, s);
+      if (rc) return rc;
+      normx2 = h.norm2;
+      if (!isfinite(normx2)) return TK_ERR_NONFINITE;
+    }
     launch_identity<double>(U64, v.I, s);
     return TK_OK;
   }
-  DevStatus h{};
-  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
-  init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, s);
-  qr_enqueue(w.Lacc, v.I, R, w.L, w.Q1, w.CL, w.Cq, &w.st->status, s);
+  init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, want_norm ? &w.st->norm2 : nullptr, s);
+  init_finish_enqueue(v, R, xdt, o.resid_mode, w, s);
   int rc = read_status(w.st, &h, s);
   if (rc) return rc;
+  if (want_norm) {
+    normx2 = h.norm2;
+    if (!isfinite(normx2)) return TK_ERR_NONFINITE;
+  }
   if (h.status) return h.status;
-  const double nA = norm_a;
+  const double nA = norm_a >= 0.0 ? norm_a : sqrt(normx2);
   double res_prev = 0.0;
   for (int k = 0;; ++k) {
-    sweep_enqueue(X, xdt, v, R, normb2, o.resid_mode, w, s);
+    sweep_enqueue(X, xdt, v, R, normx2, o.resid_mode, w, s);
     mr.sweeps++;
     rc = read_status(w.st, &h, s);
     if (rc) return rc;
@@ -321,10 +345,12 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
     mr.iters = k;
     if (k >= 1 && fabs(res_prev - res) <= o.tol * nA) { mr.converged = 1; break; }
     if (k >= o.max_iters) { mr.converged = 0; break; }
+    // the next sweep starts from L_{k+1}, whose preparation ran speculatively
+    if (h.prep_status) return h.prep_status;
     std::swap(w.L, w.Lnext);
     res_prev = res;
   }
-  qr_enqueue(w.L, v.I, R, U64, w.Q1, w.CL, w.Cq, &w.st->status, s);
+  qr_enqueue(w.L, v.I, R, U64, w.Q1, &w.st->status, s);
   rc = read_status(w.st, &h, s);
   if (rc) return rc;
   return h.status;
@@ -372,6 +398,17 @@ size_t driver_ws(int which, int xdt, int N, const int64_t* dims, const int32_t* 
 int ttm_enqueue(const void* X, int xdt, int N, const int64_t* dims, int mode, const void* M,
                 int64_t J, int trans, void* Y, hipStream_t s) {
   View v = mode_view(N, dims, mode);
+  if (fused_ttm_supported(xdt, v, J)) {
+    // matrix cores; the matrix is FP32 (the compute type of FP32 / BF16 data)
+    FusedArgs f{};
+    f.X = X; f.x_dtype = xdt; f.v = v; f.R = (int)J;
+    f.Lq = (const float*)M;
+    if (trans) { f.lq_ldi = J; f.lq_ldo = 1; }
+    else { f.lq_ldi = 1; f.lq_ldo = v.I; }
+    f.y = (float*)Y;
+    launch_fused(f, NWG_MAX, s);
+    return TK_OK;
+  }
   VpassArgs a{};
   a.X = X; a.x_dtype = xdt; a.v = v;
   a.W = M;
@@ -409,23 +446,11 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   for (int n = 0; n < N; ++n) U64[n] = (double*)ar.take((size_t)dims[n] * ranks[n] * 8);
   Arena mar(ar.base + ar.off, ar.cap - ar.off);
 
-  // ||A||^2 once (E5.01 uses the input's norm for every mode).
-  ModeWs w0;
-  {
-    Arena tmp = mar;
-    carve_mode(tmp, adt, mode_view(N, dims, 0), ranks[0], w0);
-  }
-  HIPCHK(hipMemsetAsync(w0.st, 0, sizeof(DevStatus), s));
-  norm2_enqueue(A, adt, numel(N, dims), w0.sparts, &w0.st->norm2, s);
-  DevStatus h{};
-  rc = read_status(w0.st, &h, s);
-  if (rc) return rc;
-  const double norm2 = h.norm2;
-  if (!isfinite(norm2)) return TK_ERR_NONFINITE;
-  if (info) info->norm_a = sqrt(norm2);
-
+  // ||A||^2 (E5.01 uses the input's norm for every mode) comes out of the
+  // first mode's initial pass over A; in st-HOSVD each later mode's initial
+  // pass yields ||B||^2 of the truncated tensor it sweeps.
+  double norm2 = -1.0;
   int worst = TK_OK;
-  double normb2 = norm2;
   int64_t cur[TK_MAX_ORDER];
   for (int k = 0; k < N; ++k) cur[k] = dims[k];
   const void* B = A;
@@ -438,16 +463,13 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
     ModeWs w;
     carve_mode(tmp, which == 1 ? bdt : adt, v, R, w);
     ModeResult mr;
-    if (which == 1 && t > 0) {
-      // ||B||^2 of the truncated tensor for the trace form of the residual
-      HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
-      norm2_enqueue(B, bdt, numel(N, cur), w.sparts, &w.st->norm2, s);
-      rc = read_status(w.st, &h, s);
-      if (rc) return rc;
-      normb2 = h.norm2;
+    double normb2 = (which == 1 && t > 0) ? -1.0 : norm2;
+    rc = mode_solve(which == 1 ? B : A, which == 1 ? bdt : adt, v, R, o, normb2,
+                    norm2 >= 0.0 ? sqrt(norm2) : -1.0, n, w, U64[n], mr, s);
+    if (rc == TK_OK && norm2 < 0.0) {
+      norm2 = normb2;
+      if (info) info->norm_a = sqrt(norm2);
     }
-    rc = mode_solve(which == 1 ? B : A, which == 1 ? bdt : adt, v, R, o, normb2, sqrt(norm2),
-                    n, w, U64[n], mr, s);
     if (info) {
       info->iters[n] = mr.iters;
       info->converged[n] = mr.converged;
@@ -616,7 +638,8 @@ size_t contract_allbut_workspace_bytes(int32_t dtype, int32_t N, const int64_t* 
     return 0;
   View v = mode_view(N, xdims, mode);
   int chunks = lpass_chunks(v, J, NWG_MAX);
-  return align_up((size_t)chunks * v.I * J * dsize(dtype)) + align_up(v.I * J * 8) + 256;
+  return align_up((size_t)chunks * v.I * J * dsize(dtype)) + align_up(v.I * J * 8) +
+         align_up((size_t)(REDUCE_GROUPS / 4) * v.I * J * 8) + 256;
 }
 
 int contract_allbut(const void* X, const void* Y, int32_t dtype, int32_t N,
@@ -633,15 +656,16 @@ int contract_allbut(const void* X, const void* Y, int32_t dtype, int32_t N,
   Arena ar(ws, ws_bytes);
   void* parts = ar.take((size_t)chunks * v.I * J * dsize(dtype));
   double* red = (double*)ar.take(v.I * J * 8);
+  double* rtmp = (double*)ar.take((size_t)(REDUCE_GROUPS / 4) * v.I * J * 8);
   LpassArgs a{};
   a.X = X; a.x_dtype = dtype; a.v = v; a.v_kind = 2; a.V = Y; a.R = J; a.parts = parts;
   launch_lpass(a, chunks, s);
   const int64_t n = v.I * J;
   if (dtype == TK_F64) {
-    launch_reduce_parts<double>((const double*)parts, chunks, n, n, red, s);
+    launch_reduce_parts<double>((const double*)parts, chunks, n, n, red, rtmp, s);
     launch_convert<double>(red, n, (double*)K, s);
   } else {
-    launch_reduce_parts<float>((const float*)parts, chunks, n, n, red, s);
+    launch_reduce_parts<float>((const float*)parts, chunks, n, n, red, rtmp, s);
     launch_convert<float>(red, n, (float*)K, s);
   }
   return hipGetLastError() == hipSuccess ? TK_OK : TK_ERR_HIP;
@@ -663,9 +687,8 @@ int als_init_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims
   carve_mode(ar, a_dtype, v, R, w);
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
-  norm2_enqueue(A, a_dtype, numel(N, dims), w.sparts, &w.st->norm2, s);
-  init_enqueue(A, a_dtype, v, R, seed, mode, w, (double*)Y, s);
-  qr_enqueue((const double*)Y, v.I, R, (double*)L0, w.Q1, w.CL, w.Cq, &w.st->status, s);
+  init_enqueue(A, a_dtype, v, R, seed, mode, w, (double*)Y, &w.st->norm2, s);
+  qr_enqueue((const double*)Y, v.I, R, (double*)L0, w.Q1, &w.st->status, s);
   DevStatus h{};
   int rc = read_status(w.st, &h, s);
   if (rc) return rc;
@@ -692,6 +715,15 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
   HIPCHK(hipMemcpyAsync(w.L, L, v.I * (size_t)R * 8, hipMemcpyDeviceToDevice, s));
+  {
+    // L~, its quantised Gram factor and the compute-type L for this sweep
+    StepArgs p{};
+    p.m = v.I; p.r = R; p.ops = STEP_PREP;
+    p.Qin = w.L;
+    p.Lq = w.Lq; p.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; p.Cq = w.Cq;
+    p.status = &w.st->status; p.prep_status = &w.st->prep_status;
+    launch_mode_step(p, cdtype(a_dtype), s);
+  }
   sweep_enqueue(A, a_dtype, v, R, norm2, resid_mode, w, s);
   HIPCHK(hipMemcpyAsync(L_next, w.Lnext, v.I * (size_t)R * 8, hipMemcpyDeviceToDevice, s));
   DevStatus h{};
@@ -712,9 +744,10 @@ int qr_f64(const void* L, int64_t m, int32_t r, void* Q, void* Rhat, void* ws, s
   double* C1 = (double*)ar.take(64 * 64 * 8);
   double* C2 = (double*)ar.take(64 * 64 * 8);
   DevStatus* st = (DevStatus*)ar.take(sizeof(DevStatus));
+  (void)C1; (void)C2;
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipMemsetAsync(st, 0, sizeof(DevStatus), s));
-  qr_enqueue((const double*)L, m, r, (double*)Q, Q1, C1, C2, &st->status, s);
+  qr_enqueue((const double*)L, m, r, (double*)Q, Q1, &st->status, s);
   DevStatus h{};
   int rc = read_status(st, &h, s);
   if (rc) return rc;
@@ -838,8 +871,8 @@ int autotune_batched(const BatchLaunch& L, hipStream_t s, int* best_out) {
     }
     if (ms < best) { best = ms; bc = cfg; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   *best_out = bc;
   return TK_OK;
 }
@@ -946,9 +979,9 @@ int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t count,
   if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
   if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess;
   if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
-  if (exec) hipGraphExecDestroy(exec);
-  if (graph) hipGraphDestroy(graph);
-  hipStreamDestroy(cs);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
   if (!ok) return TK_ERR_HIP;
   std::vector<int32_t> hs(count), hi(3 * (size_t)count);
   HIPCHK(hipMemcpy(hs.data(), dstatus, 4 * (size_t)count, hipMemcpyDeviceToHost));
@@ -991,8 +1024,9 @@ extern "C" int als_sweep_kernel(const void* A, int32_t a_dtype, int32_t N, const
     f.gv_parts = w.gparts;
     int nwg = launch_fused(f, NWG_MAX, s);
     if (reduce) {
-      launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Lacc, s);
-      launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, (int64_t)R * R, (int64_t)R * R, GV, s);
+      launch_reduce_parts<float>((const float*)w.parts, nwg, IR, IR, Lacc, w.rtmp, s);
+      launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, (int64_t)R * R, (int64_t)R * R, GV,
+                                  w.rtmp, s);
     }
   } else {
     VpassArgs a{};
@@ -1009,8 +1043,8 @@ extern "C" int als_sweep_kernel(const void* A, int32_t a_dtype, int32_t N, const
     int chunks = lpass_chunks(v, R, NWG_MAX);
     launch_lpass(l, chunks, s);
     if (reduce) {
-      launch_reduce_parts<double>(w.gparts, gch, (int64_t)R * R, (int64_t)R * R, GV, s);
-      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, Lacc, s);
+      launch_reduce_parts<double>(w.gparts, gch, (int64_t)R * R, (int64_t)R * R, GV, w.rtmp, s);
+      launch_reduce_parts<float>((const float*)w.parts, chunks, IR, IR, Lacc, w.rtmp, s);
     }
   }
   return hipGetLastError() == hipSuccess ? TK_OK : TK_ERR_HIP;

@@ -24,17 +24,13 @@ template <> struct Store<bf16_t> {
 };
 
 // ---------------------------------------------------------------- small LA
-template <typename T>
-void launch_gram(const T* X, int64_t m, int r, double* G, hipStream_t s);
-void launch_chol(double* G, int r, int* status, hipStream_t s);
-template <typename TO>
-void launch_row_solve(const double* B, int64_t m, int r, const double* C, int gram,
-                      TO* X, double* Xd, hipStream_t s);
-void launch_trace_resid(const double* Cq, const double* D, int r, double norm2,
-                        const double* explicit_sum, double* out, hipStream_t s);
+// out[e] = sum_w in[w*stride + e] in FP64, fixed order.  With tmp (room for
+// REDUCE_GROUPS / 4 * n doubles) the sum runs in two stages over up to
+// REDUCE_GROUPS interleaved part groups; without it, in one.
+constexpr int REDUCE_GROUPS = 256;
 template <typename T>
 void launch_reduce_parts(const T* in, int parts, int64_t n, int64_t stride, double* out,
-                         hipStream_t s);
+                         double* tmp, hipStream_t s);
 template <typename T>
 void launch_identity(T* U, int64_t n, hipStream_t s);
 template <typename T>
@@ -69,6 +65,8 @@ struct LpassArgs {
   void* parts; double* norm2_parts;
 };
 int lpass_chunks(const View& v, int64_t R, int nwg_max);
+// Workgroups of an L-pass over `chunks` fibre chunks (one norm2 partial each).
+int lpass_blocks(const View& v, int chunks);
 void launch_lpass(const LpassArgs& a, int chunks, hipStream_t s);
 
 // G = V^T V partials over row chunks: parts[c*R*R + a*R + b] (FP64).
@@ -82,22 +80,46 @@ void launch_norm2_parts(const void* X, int x_dtype, int64_t n, int chunks, doubl
 // Fused ALS sweep on the matrix cores (FP32/BF16 storage, I <= 256, R <= 64):
 // one read of every fibre a_j gives v_j = Lq^T a_j, G_V += v_j v_j^T and
 // L_acc += a_j v_j^T (and, with resid, sum ||a_j - Lr v_j||^2).
+// TTM variant (y != null): Y[p, r, q] = sum_i Lq(i, r) X[p, i, q] with
+// Lq(i, r) = Lq[i*lq_ldi + r*lq_ldo] (lq_ldi == 0: row-major I x R).
 struct FusedArgs {
   const void* X; int x_dtype; View v; int R;
   const float* Lq;       // I x R, quantised L~ (compute type float)
   const float* Lr;       // I x R, factor for the explicit residual (or null)
   float* lacc_parts;     // [nwg][I][R]
   double* gv_parts;      // [FUSED_WAVES * nwg][R][R]
-  double* resid_parts;   // [FUSED_WAVES * nwg] (only when Lr != null)
+  double* resid_parts;   // [FUSED_WAVES * nwg] (explicit residual)
   int sketch; uint64_t seed; int mode;  // init variant: V = sketch, no G_V
-  double* norm2_parts;   // [nwg] (init variant)
+  double* norm2_parts;   // [FUSED_WAVES * nwg] sums of X^2 (init variant, optional)
+  float* y;              // TTM output (or null)
+  int64_t lq_ldi, lq_ldo;
 };
 // Shapes the fused kernel takes (LDS budget), for the given residual mode.
 bool fused_supported(int x_dtype, const View& v, int R, int resid_mode);
+// Shapes its TTM variant takes (J output rows of the mode).
+bool fused_ttm_supported(int x_dtype, const View& v, int64_t J);
 // Launches and returns the number of workgroups W; L_acc partials are
 // [W][I][R], Gram and residual partials [FUSED_WAVES * W] (one per wave).
 constexpr int FUSED_WAVES = 8;
 int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
+
+// One-workgroup FP64 steps of the mode solve (see k_mode_step.hip).
+enum { STEP_SOLVE = 1, STEP_QR = 2, STEP_PREP = 4, STEP_PREP_SPECULATIVE = 8 };
+struct StepArgs {
+  int64_t m; int r; int ops;
+  // SOLVE: Lnext = Lacc GV^{-1}; res2[0] = rsum ? *rsum : norm2 - tr(Gq^-1 GV),
+  // res2[1] = tr(Gq^-1 GV) with Gq = Cq Cq^T (Cq as left by the last PREP)
+  const double* Lacc; const double* GV; double* Lnext;
+  double norm2; const double* rsum; double* res2;
+  // QR: Qout = Q of the reduced QR of Qin (Q1: m x r scratch)
+  const double* Qin; double* Q1; double* Qout;
+  // PREP from Lnext (SOLVE) or Qout (QR): Lq = L (L^T L)^{-1} in the compute
+  // type, Cq = chol(Lq^T Lq), Lr = L in the compute type (if non-null)
+  void* Lq; void* Lr; double* Cq;
+  int* status;        // failures of SOLVE / QR / non-speculative PREP
+  int* prep_status;   // failures of a speculative PREP
+};
+void launch_mode_step(const StepArgs& a, int q_dtype, hipStream_t s);
 
 // Batched st-HOSVD-ALS of small order-3 FP32 tensors (I_n <= 128,
 // R_n <= 16): one persistent launch, one tensor per workgroup at a time.

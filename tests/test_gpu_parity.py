@@ -49,6 +49,8 @@ TTM_CASES = [
     ((5, 200, 66), 1, 20, True),    # truncation 200 -> 20, ragged fibre tiles
     ((3, 4, 5, 6), 3, 2, False),
     ((65, 129), 0, 70, False),      # order 2, more outputs than one chunk
+    ((300, 150), 1, 37, True),      # Q == 1, 48-wide rank padding, ragged fibre tiles
+    ((33, 256, 17), 1, 48, False),  # largest mode and output width of the MFMA TTM
 ]
 
 
