@@ -148,8 +148,8 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   constexpr int LRS = RP + 1;                // Lr row stride
   constexpr int NG = NR * (NR + 1) / 2;      // Gram output tiles
   constexpr int U1 = (4 * NR + NW - 1) / NW; // R-update tiles per wave (max)
-  constexpr int U2 = 2 * NR;                 // L-update tiles per wave (max)
-  constexpr bool NFIX = (NW % NR) == 0;      // a wave's L-update rank tile is fixed
+  constexpr int RT = IC == 32 ? 2 : 1;       // L-update row tiles per wave (MT <= 8 RT)
+  constexpr int U2 = RT * NR;                // L-update tiles per wave
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
@@ -183,9 +183,6 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 
   // R-update tiles: t = w + NW u -> (fibre block t / NR, rank tile t % NR)
   const int cnt1 = 4 * NR > w ? (4 * NR - w + NW - 1) / NW : 0;
-  // L-update tiles: t = w + NW u -> (row tile t / NR, rank tile t % NR)
-  const int nt2 = MT * NR;
-  const int cnt2 = nt2 > w ? (nt2 - w + NW - 1) / NW : 0;
   f4 lacc[U2];
 #pragma unroll
   for (int u = 0; u < U2; ++u) lacc[u] = f4{0, 0, 0, 0};
@@ -202,23 +199,29 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   const T* X = (const T*)a.X;
   const int64_t ntiles = ceil_div(J, TJ);
   const int nwg = gridDim.x;
-  T pf[IC];
-  bool pf_ok = false;
+  // Two register buffers: while a tile is processed from LDS the next two
+  // are in flight (two tiles of loads per wave, under the 63-load limit).
+  T pf0[IC], pf1[IC];
+  bool ok0 = false, ok1 = false;
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf, pf_ok);
+  if (tile < ntiles) prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf0, ok0);
+  if (tile + nwg < ntiles) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf1, ok1);
 
-  for (; tile < ntiles; tile += nwg) {
+  auto body = [&](const int64_t tile, T (&pf)[IC], bool& pf_ok) __attribute__((always_inline)) {
     const int64_t j0 = tile * TJ;
     __syncthreads();
     if (MODE == 2 && want_norm) stash<T, LAYOUT, IC, true>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
     else stash<T, LAYOUT, IC, false>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
     __syncthreads();
-    if (tile + nwg < ntiles) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
+    // this buffer now fetches the tile after the one the other buffer holds
+    if (tile + 2 * nwg < ntiles)
+      prefetch<T, LAYOUT, IC>(X, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
 
     if (MODE != 2) {
       // R-update: tile (fibre block f, rank tile n): A = X^T (16 fibres x
-      // 4 rows), B = Lq (4 rows x 16 ranks), K = I in steps of 4.  Four K
-      // steps per stage; the next stage's operands are read first.
+      // 4 rows), B = Lq (4 rows x 16 ranks), K = the MT 16-row stages of
+      // the tile (rows I..16 MT - 1 of X and Lq are zero).  The operands of
+      // the next stage are read before the four MFMAs of the current one.
 #pragma unroll
       for (int u = 0; u < U1; ++u) {
         if (u < cnt1) {
@@ -227,23 +230,27 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
           const float* xa = Xs + lk * XLD + 16 * fb + lr;
           const float* lb = Lq + lk * RS + 16 * n + lr;
           f4 vacc = f4{0, 0, 0, 0};
-          float ac[4], bc[4], an[4], bn[4];
-          auto stage = [&](int ks, float (&aa)[4], float (&bb)[4]) {
+          float ca[4], cb[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            ca[q] = xa[4 * q * XLD];
+            cb[q] = lb[4 * q * RS];
+          }
+          for (int st = 0; st < MT; ++st) {
+            const int nx = 16 * (st + 1 < MT ? st + 1 : st);
+            float na[4], nb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const bool in = ks + q < KS;
-              const int k = in ? ks + q : 0;
-              aa[q] = in ? xa[4 * k * XLD] : 0.0f;
-              bb[q] = lb[4 * k * RS];
+              na[q] = xa[(nx + 4 * q) * XLD];
+              nb[q] = lb[(nx + 4 * q) * RS];
             }
-          };
-          stage(0, ac, bc);
-          for (int ks = 0; ks < KS; ks += 4) {
-            stage(ks + 4, an, bn);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) vacc = mfma16(ac[q], bc[q], vacc);
+            for (int q = 0; q < 4; ++q) vacc = mfma16(ca[q], cb[q], vacc);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { ac[q] = an[q]; bc[q] = bn[q]; }
+            for (int q = 0; q < 4; ++q) {
+              ca[q] = na[q];
+              cb[q] = nb[q];
+            }
           }
           // V[16 fb + 4 lk + q][16 n + lr] = vacc[q]
           if (MODE == 3) {
@@ -286,39 +293,40 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
           if (j0 + jl < J) Y[(j0 + jl) * R + r] = Vf[r * (TJ + 1) + jl];
         }
       }
-      continue;
+      return;
     }
 
     // L-update: tile (m, n) += X[16m.., f] V[f, 16n..] over the 64 fibres.
+    // Wave w owns the row tiles m = w + NW rt (rt < RT; clamped into the
+    // mode, duplicates are never stored) for every rank tile n; the RT * NR
+    // independent accumulations are interleaved per K step.
     {
-      constexpr int NB = NFIX ? 1 : NR;        // rank tiles cached in registers
-      float vb[NB][16];
-      const int nfix = w % NR;
+      float vb[NR][16];
 #pragma unroll
-      for (int nn = 0; nn < NB; ++nn) {
-        const int n = NFIX ? nfix : nn;
+      for (int n = 0; n < NR; ++n)
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) vb[nn][ks] = Vf[(4 * ks + lk) * RS + 16 * n + lr];
+        for (int ks = 0; ks < 16; ++ks) vb[n][ks] = Vf[(4 * ks + lk) * RS + 16 * n + lr];
+      const float* xr[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int m = min(w + NW * rt, MT - 1);
+        xr[rt] = Xs + (16 * m + lr) * XLD + lk;
       }
+      float ca[RT];
 #pragma unroll
-      for (int u = 0; u < U2; ++u) {
-        if (u < cnt2) {
-          const int t = w + NW * u;
-          const int m = t / NR, n = t % NR;
-          const float* xr = Xs + (16 * m + lr) * XLD + lk;
-          float xa4[16];
+      for (int rt = 0; rt < RT; ++rt) ca[rt] = xr[rt][0];
 #pragma unroll
-          for (int ks = 0; ks < 16; ++ks) xa4[ks] = xr[4 * ks];
+      for (int ks = 0; ks < 16; ++ks) {
+        float na[RT];
 #pragma unroll
-          for (int ks = 0; ks < 16; ++ks) {
-            float bsel = vb[0][ks];
-            if (!NFIX) {
+        for (int rt = 0; rt < RT; ++rt) na[rt] = xr[rt][4 * (ks + 1 < 16 ? ks + 1 : ks)];
 #pragma unroll
-              for (int nn = 1; nn < NB; ++nn) bsel = (n == nn) ? vb[nn][ks] : bsel;
-            }
-            lacc[u] = mfma16(xa4[ks], bsel, lacc[u]);
-          }
-        }
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int n = 0; n < NR; ++n)
+            lacc[rt * NR + n] = mfma16(ca[rt], vb[n][ks], lacc[rt * NR + n]);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) ca[rt] = na[rt];
       }
 
       if (MODE != 2) {
@@ -362,6 +370,12 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
           if (16 * m + 4 * lk + q < I) rsum += (double)c[q] * (double)c[q];
       }
     }
+  
+  };
+
+  for (; tile < ntiles; tile += 2 * nwg) {
+    body(tile, pf0, ok0);
+    if (tile + nwg < ntiles) body(tile + nwg, pf1, ok1);
   }
 
   // ---- per-workgroup outputs
@@ -375,14 +389,16 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
   float* lp = a.lacc_parts + (int64_t)wg * I * R;
 #pragma unroll
-  for (int u = 0; u < U2; ++u) {
-    if (u < cnt2) {
-      const int t = w + NW * u;
-      const int m = t / NR, n = t % NR;
+  for (int rt = 0; rt < RT; ++rt) {
+    const int m = w + NW * rt;
+    if (m < MT) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = 16 * m + 4 * lk + q, r = 16 * n + lr;
-        if (i < I && r < R) lp[i * R + r] = lacc[u][q];
+      for (int n = 0; n < NR; ++n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * m + 4 * lk + q, r = 16 * n + lr;
+          if (i < I && r < R) lp[i * R + r] = lacc[rt * NR + n][q];
+        }
       }
     }
   }
