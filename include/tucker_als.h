@@ -70,8 +70,10 @@ typedef enum {
 } tk_status;
 
 /* Residual evaluation inside the ALS sweep (stop test, eq. E5.01).
- * TK_RESID_TRACE: res^2 = ||A||^2 - tr(G_L' G_V) from FP64 Grams, where G_L'
- *   belongs to the factor actually used by the sweep (no extra tensor work).
+ * TK_RESID_TRACE: res^2 = ||B||^2 - tr(G_L'^{-1} G_V) from FP64 Grams, where B
+ *   is the tensor being swept (A, or the truncated tensor of st-HOSVD), G_V =
+ *   R^T R and G_L' is the Gram of the quantised L (L^T L)^{-1} the sweep
+ *   actually used (no extra tensor work; ||B||^2 comes from the initial pass).
  * TK_RESID_EXPLICIT: res^2 = sum_j ||a_j - L v_j||^2 accumulated during the
  *   sweep from the fibres themselves (one more small contraction per fibre;
  *   no extra HBM traffic). */
