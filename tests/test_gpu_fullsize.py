@@ -1,0 +1,147 @@
+"""Checks at the full size of the benchmark workload (200^4 FP32 tensor, core 20^4 with
+exp(-(i+j+k+l)/10) decay, 1e-4 relative noise, ranks 20, eta = 1e-4) in the launch
+configuration bench.py times: outputs the oracle computes one by one (sampled TTM
+entries) and properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tucker_oracle as o
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (200, 200, 200, 200)
+R = 20
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big(gpu_lib):
+    flush("generating the 200^4 FP32 workload")
+    w = synth.workload_4way_torch(DIMS, R, 1e-4)
+    torch.cuda.synchronize()
+    yield w
+    del w
+    torch.cuda.empty_cache()
+
+
+def _fibre(A, mode, idx):
+    """Fibre of A along `mode` at the other indices idx (tuple of N-1 ints)."""
+    sl = list(idx)
+    sl.insert(mode, slice(None))
+    return A[tuple(sl)].double().cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_fullsize_ttm_sampled(gpu_lib, big, mode):
+    """Y = A x_n U^T at 200^4 (mode 1: P = 1; mode 4: Q = 1): 64 sampled fibres of Y
+    against the oracle's TTM of the same fibres of A, within the FP32 accumulation bound."""
+    tk = gpu_lib
+    A = big["A"]
+    rng = np.random.default_rng(71 + mode)
+    U = synth.orthonormal(rng, 200, R).astype(np.float32)
+    flush(f"fullsize ttm mode={mode}")
+    Y = tk.ttm(A, torch.from_numpy(U).cuda(), mode, transpose=True)
+    assert tuple(Y.shape) == tuple(R if k == mode else 200 for k in range(4))
+    Uh = U.astype(np.float64)
+    for _ in range(64):
+        idx = tuple(int(rng.integers(0, 200)) for _ in range(3))
+        a = _fibre(A, mode, idx)
+        want = o.ttm(a[:, None], Uh.T, 0)[:, 0]
+        got = _fibre(Y, mode, idx)
+        bound = 200 * 2.0 ** -24 * (np.abs(Uh).T @ np.abs(a))
+        assert np.all(np.abs(got - want) <= 4 * bound + 1e-30), (idx, np.abs(got - want).max())
+
+
+@pytest.mark.parametrize("mode", [0, 3])
+def test_fullsize_sweep_kernel_identity(gpu_lib, big, mode):
+    """One fused sweep at full size: with V = A_(n)^T Lq, L_acc = A_(n) V and
+    G_V = V^T V satisfy tr(Lq^T L_acc) = tr(G_V); G_V is symmetric positive definite."""
+    tk = gpu_lib
+    A = big["A"]
+    rng = np.random.default_rng(80 + mode)
+    Lq = torch.from_numpy(rng.standard_normal((200, R)) / 200.0).float().cuda()
+    flush(f"fullsize sweep kernel mode={mode}")
+    Lacc, GV = tk.als_sweep_kernel(A, mode, Lq)
+    lhs = float((Lq.double() * Lacc.double()).sum())
+    rhs = float(torch.trace(GV.double()))
+    # FP32 accumulation of L_acc over ~3e4 fibres per workgroup: ~1e-5 relative
+    assert abs(lhs - rhs) <= 1e-4 * abs(rhs), (lhs, rhs)
+    G = GV.double().cpu().numpy()
+    np.testing.assert_allclose(G, G.T, rtol=0, atol=1e-12 * np.abs(G).max())
+    assert np.linalg.eigvalsh(G).min() > 0
+
+
+def _relerr_and_core_norm(tk, A, G, Us):
+    """||A - A_hat|| / ||A|| in FP64 over slabs of mode 1, and ||A||."""
+    Ah = tk.tucker_reconstruct(G, Us)
+    num = 0.0
+    den = 0.0
+    for s in range(0, A.shape[0], 20):
+        a = A[s:s + 20].double()
+        num += float(((a - Ah[s:s + 20].double()) ** 2).sum())
+        den += float((a * a).sum())
+    del Ah
+    return (num / den) ** 0.5, den ** 0.5
+
+
+def test_fullsize_sthosvd_properties(gpu_lib, big):
+    """The benchmark call itself: orthonormal factors, Pythagoras with the core,
+    the st-HOSVD error identity with the solver's own residuals, error at the noise
+    floor, and factors that span the generating subspaces."""
+    tk = gpu_lib
+    A = big["A"]
+    flush("fullsize st-HOSVD-ALS FP32")
+    G, Us, info = tk.als_sthosvd(A, (R,) * 4, tol=1e-4)
+    assert info["status"] == "TK_OK"
+    for U in Us:
+        Uh = U.double().cpu().numpy()
+        np.testing.assert_allclose(Uh.T @ Uh, np.eye(R), atol=1e-5)
+    e, nA = _relerr_and_core_norm(tk, A, G, Us)
+    assert abs(nA - info["norm_a"]) <= 1e-9 * nA
+    # 1e-4 relative noise, nearly all of it outside the 20^4 signal subspace
+    assert 0.99e-4 <= e <= 1.01e-4, e
+    g2 = float((G.double() ** 2).sum())
+    assert abs(nA ** 2 - (g2 + (e * nA) ** 2)) <= 1e-6 * nA ** 2
+    # st-HOSVD: ||A - A_hat||^2 = sum_n res_n^2 (successive orthogonal projections).
+    # These residuals come from the trace form ||B||^2 - tr(G_q^-1 G_V), whose absolute
+    # error is ~1e-9 ||B||^2 (FP32 rounding of V); here res^2 ~ 1e-8 ||B||^2, so the
+    # identity holds to ~10% (the stop test only needs res to a few % of eta ||A||).
+    s2 = sum(r * r for r in info["resid"][:4])
+    assert abs(s2 - (e * nA) ** 2) <= 0.15 * (e * nA) ** 2, (s2, (e * nA) ** 2)
+    for U, Ut in zip(Us, big["factors"]):
+        ang = o.principal_angles(U.double().cpu().numpy(), Ut)
+        assert ang.max() < 1e-2, ang.max()
+
+
+def test_fullsize_sthosvd_explicit_residual(gpu_lib, big):
+    """Same call with the residual accumulated explicitly in the fused sweep: the
+    st-HOSVD error identity then holds to 1%, and the factors match the trace-form run."""
+    tk = gpu_lib
+    A = big["A"]
+    flush("fullsize st-HOSVD-ALS FP32, explicit residual")
+    G, Us, info = tk.als_sthosvd(A, (R,) * 4, tol=1e-4, resid_mode="explicit")
+    assert info["status"] == "TK_OK"
+    e, nA = _relerr_and_core_norm(tk, A, G, Us)
+    assert 0.99e-4 <= e <= 1.01e-4, e
+    s2 = sum(r * r for r in info["resid"][:4])
+    assert abs(s2 - (e * nA) ** 2) <= 0.01 * (e * nA) ** 2, (s2, (e * nA) ** 2)
+
+
+def test_fullsize_sthosvd_bf16_storage(gpu_lib, big):
+    """BF16 storage of the same tensor: error against the FP32 tensor within the
+    BF16 gate of the FP32 result."""
+    tk = gpu_lib
+    A = big["A"]
+    Ab = A.to(torch.bfloat16)
+    flush("fullsize st-HOSVD-ALS BF16 storage")
+    G, Us, info = tk.als_sthosvd(Ab, (R,) * 4, tol=1e-4)
+    assert info["status"] in ("TK_OK", "TK_NOT_CONVERGED")
+    del Ab
+    e, _ = _relerr_and_core_norm(tk, A, G, Us)
+    assert e <= 1e-4 + 1e-2, e
+    assert e <= 1.2e-4, e   # observed ~1.02e-4: BF16 rounding falls outside the subspace
