@@ -1,0 +1,417 @@
+// Fused ALS sweep for BF16 storage on the gfx950 BF16 matrix cores.
+//
+// Same products as k_fused.hip (one read of every fibre a_j per sweep,
+// row-wise rule of Section 3):  v_j = Lq^T a_j,  G_V += v_j v_j^T,
+// L_acc += a_j v_j^T; the init variant uses the Section 5 sketch rows for
+// v_j (and adds up ||A||^2), the TTM variant writes v_j out as fibre j of
+// B x_n U^T.  The tensor is BF16, so its products with BF16 operands are
+// exact in FP32.  The FP32 operands (Lq, V, the sketch) are split exactly
+// into three BF16 terms (h + m + l equals the FP32 value: each split
+// removes the leading 8 significant bits of a 24-bit significand), so every
+// product is the exact FP32-operand product and only the order of the FP32
+// accumulation differs from the FP32 matrix-core path.  G_V stays on the
+// FP32 matrix cores from the FP32 V (the trace residual needs it).
+//
+// Work layout: 256 persistent workgroups of 8 waves walk tiles of TJ = 128
+// fibres (view [P, I, Q] with Q even: each lane loads one dword holding two
+// adjacent fibres of a row).  The tile is kept in LDS as BF16 rows whose
+// 16-byte chunks are XOR-swizzled by row, so the eight-row column gathers
+// of the R-update hit distinct banks while the L-update reads contiguous
+// 16-byte runs of fibres.
+//   R-update  wave w owns fibre block w (16 fibres) for every rank tile:
+//             v_mfma_f32_16x16x32_bf16, A = X^T gathered (16 fibres x 32
+//             rows), B = Lq^T splits (32 rows x 16 ranks), K = 32-row stages;
+//   L-update  wave w owns row tiles w + 8 rt for every rank tile:
+//             v_mfma_f32_16x16x32_bf16, A = X (16 rows x 32 fibres), B = V
+//             splits (32 fibres x 16 ranks), K = the 128 fibres;
+//   Gram      v_mfma_f32_16x16x4f32 on the FP32 V, wave w: fibres 16w..16w+15.
+// Every reduction has a fixed order (deterministic, no atomics).
+#include "tk_kernels.h"
+
+namespace tk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int NT = 512;
+constexpr int NW = NT / 64;
+static_assert(NW == FUSED_WAVES, "partial buffers are sized for FUSED_WAVES waves");
+constexpr int TJ = 128;            // fibres per tile
+constexpr int XS = TJ + 8;         // LDS row stride of the tile (BF16 elements)
+constexpr int VS = TJ + 8;         // row stride of the V^T splits
+constexpr int NWG = 256;
+
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// v = h + m + l exactly (three round-to-nearest BF16 terms).
+__device__ __forceinline__ void split3(float v, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)v;
+  const float r1 = v - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
+
+__host__ __device__ constexpr int rank_stride(int RP) { return (RP % 32 == 0) ? RP + 16 : RP; }
+
+// Element (row, fibre f) of the swizzled tile: 16-byte chunk f / 8 of the
+// row is stored at chunk (f / 8) ^ (2 ((row / 8) & 3)).
+__device__ __forceinline__ int xidx(int row, int f) {
+  return row * XS + ((((f >> 3) ^ (((row >> 3) & 3) << 1))) << 3) + (f & 7);
+}
+
+struct LdsB {
+  int xs, lq, vt, vf, total;  // offsets in bytes
+};
+
+__host__ __device__ inline LdsB lds_b16(int I, int NR, int mode) {
+  const int RP = 16 * NR;
+  const int XR = 32 * ((I + 31) / 32);
+  const int LS = XR + 8;
+  LdsB l;
+  l.xs = 0;
+  l.lq = l.xs + (XR + 1) * XS * 2;                        // + spare row
+  l.vt = l.lq + (mode != 2 ? 3 * RP * LS * 2 : 0);
+  l.vf = l.vt + (mode != 3 ? 3 * RP * VS * 2 : 0);
+  const int vf_floats = mode == 0 ? TJ * rank_stride(RP) : (mode == 3 ? RP * (TJ + 1) : 0);
+  l.total = l.vf + vf_floats * 4;
+  return l;
+}
+
+// Prefetch: slot k is row 8k + w (clamped) of the fibre pair j0 + 2 lane,
+// j0 + 2 lane + 1 (one dword; Q even keeps pairs inside one p and aligned).
+template <int IC>
+__device__ __forceinline__ void prefetch(const uint32_t* __restrict__ X2, const View& v,
+                                         int64_t j0, int lane, int w, uint32_t* pf, bool& ok) {
+  const int64_t J = v.J();
+  const int I = (int)v.I;
+  const int64_t j = j0 + 2 * lane;
+  ok = j < J;
+  const uint32_t* b = X2 + (v.fibre_base(ok ? j : j0) >> 1);
+  const int64_t q2 = v.Q >> 1;
+#pragma unroll
+  for (int k = 0; k < IC; ++k) {
+    const int ii = min(NW * k + w, I - 1);
+    pf[k] = b[(int64_t)ii * q2];
+  }
+}
+
+template <int IC, bool NORM>
+__device__ __forceinline__ void stash(const View& v, int lane, int w, const uint32_t* pf,
+                                      bool ok, int XR, uint32_t* Xs32, double& nsum) {
+  const int I = (int)v.I;
+#pragma unroll
+  for (int k = 0; k < IC; ++k) {
+    const int ii = NW * k + w;
+    const int row = ii < I ? ii : XR;
+    const uint32_t x = ok ? pf[k] : 0u;
+    Xs32[xidx(row, 2 * lane) >> 1] = x;
+    if (NORM && ii < I) {
+      const float a = bf16_to_f32((bf16_t)(x & 0xffffu)), b = bf16_to_f32((bf16_t)(x >> 16));
+      nsum += (double)a * (double)a + (double)b * (double)b;
+    }
+  }
+}
+
+// MODE 0: sweep; 2: init (sketch, norm, no Gram); 3: TTM.
+template <int NR, int MODE, int IC>
+__global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int RP = 16 * NR;
+  constexpr int RS = rank_stride(RP);
+  constexpr int NG = NR * (NR + 1) / 2;
+  constexpr int RT = IC == 32 ? 2 : 1;        // L-update row tiles per wave (MT <= 8 RT)
+  const View v = a.v;
+  const int I = (int)v.I, R = a.R;
+  const int64_t J = v.J();
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int XR = 32 * ((I + 31) / 32);
+  const int LS = XR + 8;
+  const int MT = (I + 15) / 16;               // 16-row tiles of the mode (L-update)
+  const int ST = XR / 32;                     // 32-row stages (R-update)
+  const LdsB L = lds_b16(I, NR, MODE);
+  __bf16* Xs = (__bf16*)(smem + L.xs);
+  uint32_t* Xs32 = (uint32_t*)(smem + L.xs);
+  __bf16* Lq = (__bf16*)(smem + L.lq);        // [3][RP][LS]: Lq^T splits
+  __bf16* Vt = (__bf16*)(smem + L.vt);        // [3][RP][VS]: V^T splits
+  float* Vf = (float*)(smem + L.vf);
+
+  // ---- once per kernel: zero the tile (rows I..XR-1 stay zero), Lq splits
+  for (int e = threadIdx.x; e < (XR + 1) * XS / 2; e += NT) Xs32[e] = 0u;
+  if (MODE != 2) {
+    const int64_t ldi = a.lq_ldi ? a.lq_ldi : R, ldo = a.lq_ldi ? a.lq_ldo : 1;
+    for (int e = threadIdx.x; e < RP * LS; e += NT) {
+      const int r = e / LS, i = e - r * LS;
+      const float x = (i < I && r < R) ? a.Lq[i * ldi + r * ldo] : 0.0f;
+      __bf16 h, m, l;
+      split3(x, h, m, l);
+      Lq[(0 * RP + r) * LS + i] = h;
+      Lq[(1 * RP + r) * LS + i] = m;
+      Lq[(2 * RP + r) * LS + i] = l;
+    }
+  }
+
+  f4 lacc[RT][NR];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int n = 0; n < NR; ++n) lacc[rt][n] = f4{0, 0, 0, 0};
+  f4 gacc[NG];
+  double gd[NG][4];
+#pragma unroll
+  for (int p = 0; p < NG; ++p) {
+    gacc[p] = f4{0, 0, 0, 0};
+    gd[p][0] = gd[p][1] = gd[p][2] = gd[p][3] = 0.0;
+  }
+  double nsum = 0.0;
+  const bool want_norm = MODE == 2 && a.norm2_parts != nullptr;
+
+  const uint32_t* X2 = (const uint32_t*)a.X;
+  const int64_t ntiles = ceil_div(J, TJ);
+  const int nwg = gridDim.x;
+  uint32_t pf0[IC], pf1[IC];
+  bool ok0 = false, ok1 = false;
+  int64_t tile = blockIdx.x;
+  if (tile < ntiles) prefetch<IC>(X2, v, tile * TJ, lane, w, pf0, ok0);
+  if (tile + nwg < ntiles) prefetch<IC>(X2, v, (tile + nwg) * TJ, lane, w, pf1, ok1);
+
+  auto body = [&](const int64_t tile, uint32_t (&pf)[IC], bool& pf_ok) __attribute__((always_inline)) {
+    const int64_t j0 = tile * TJ;
+    __syncthreads();
+    if (MODE == 2 && want_norm) stash<IC, true>(v, lane, w, pf, pf_ok, XR, Xs32, nsum);
+    else stash<IC, false>(v, lane, w, pf, pf_ok, XR, Xs32, nsum);
+    __syncthreads();
+    if (tile + 2 * nwg < ntiles) prefetch<IC>(X2, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
+
+    if (MODE != 2) {
+      // R-update: fibre block w, all rank tiles; A = the eight rows
+      // 32 st + 8 lk + e of fibre 16 w + lr (one swizzled column), B = the
+      // three Lq^T splits of rank 16 n + lr over the same rows.
+      const int f = 16 * w + lr;
+      f4 vacc[NR];
+#pragma unroll
+      for (int n = 0; n < NR; ++n) vacc[n] = f4{0, 0, 0, 0};
+      for (int st = 0; st < ST; ++st) {
+        const int row0 = 32 * st + 8 * lk;
+        const __bf16* xc = Xs + xidx(row0, f);   // same swizzle for rows row0..row0+7
+        bf8 av;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
+#pragma unroll
+        for (int n = 0; n < NR; ++n) {
+#pragma unroll
+          for (int s = 0; s < 3; ++s) {
+            const bf8 bv = *(const bf8*)(Lq + (s * RP + 16 * n + lr) * LS + row0);
+            vacc[n] = mfma_bf16(av, bv, vacc[n]);
+          }
+        }
+      }
+      // V[16 w + 4 lk + q][16 n + lr] = vacc[n][q]
+#pragma unroll
+      for (int n = 0; n < NR; ++n) {
+        if (MODE == 3) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Vf[(16 * n + lr) * (TJ + 1) + 16 * w + 4 * lk + q] = vacc[n][q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Vf[(16 * w + 4 * lk + q) * RS + 16 * n + lr] = vacc[n][q];
+          __bf16 h[4], m[4], l[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) split3(vacc[n][q], h[q], m[q], l[q]);
+          const int o = (16 * n + lr) * VS + 16 * w + 4 * lk;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            Vt[0 * RP * VS + o + q] = h[q];
+            Vt[1 * RP * VS + o + q] = m[q];
+            Vt[2 * RP * VS + o + q] = l[q];
+          }
+        }
+      }
+    } else {
+      // init: V = the Section 5 sketch rows of this tile (24-bit values,
+      // split exactly)
+      for (int e = threadIdx.x; e < TJ * RP; e += NT) {
+        const int jl = e / RP, r = e - (e / RP) * RP;
+        const int64_t j = j0 + jl;
+        float s = 0.0f;
+        if (j < J && r < R)
+          s = sketch_value(a.seed, ((uint64_t)a.mode << 48) + (uint64_t)(j * R + r));
+        __bf16 h, m, l;
+        split3(s, h, m, l);
+        Vt[(0 * RP + r) * VS + jl] = h;
+        Vt[(1 * RP + r) * VS + jl] = m;
+        Vt[(2 * RP + r) * VS + jl] = l;
+      }
+    }
+    __syncthreads();
+
+    if (MODE == 3) {
+      // fibre j of Y = B x_n U^T: Y[p, r, q] = V[j, r], coalesced along q
+      float* Y = a.y;
+      for (int half = 0; half < 2; ++half) {
+        const int jl = lane + 64 * half;
+        const int64_t j = j0 + jl;
+        if (j < J) {
+          const int64_t p = j / v.Q, q = j - p * v.Q;
+          float* yb = Y + p * (int64_t)R * v.Q + q;
+          for (int r = w; r < R; r += NW) yb[(int64_t)r * v.Q] = Vf[r * (TJ + 1) + jl];
+        }
+      }
+      return;
+    }
+
+    // L-update: row tiles m = w + 8 rt (clamped; duplicates never stored),
+    // every rank tile, K = the 128 fibres in 4 steps of 32.
+    {
+      const __bf16* xr[RT];
+      int rowm[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int m = min(w + NW * rt, MT - 1);
+        rowm[rt] = 16 * m + lr;
+        xr[rt] = Xs;
+      }
+#pragma unroll
+      for (int ks = 0; ks < TJ / 32; ++ks) {
+        bf8 av[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          av[rt] = *(const bf8*)(xr[rt] + xidx(rowm[rt], 32 * ks + 8 * lk));
+#pragma unroll
+        for (int n = 0; n < NR; ++n) {
+#pragma unroll
+          for (int s = 0; s < 3; ++s) {
+            const bf8 bv = *(const bf8*)(Vt + (s * RP + 16 * n + lr) * VS + 32 * ks + 8 * lk);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) lacc[rt][n] = mfma_bf16(av[rt], bv, lacc[rt][n]);
+          }
+        }
+      }
+    }
+
+    if (MODE == 0) {
+      // Gram over fibres 16w..16w+15 (4 K steps), upper block triangle.
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        float g[NR];
+#pragma unroll
+        for (int n = 0; n < NR; ++n) g[n] = Vf[(16 * w + 4 * kk + lk) * RS + 16 * n + lr];
+        int p = 0;
+#pragma unroll
+        for (int na = 0; na < NR; ++na)
+#pragma unroll
+          for (int nb = na; nb < NR; ++nb, ++p) gacc[p] = mfma_f32(g[na], g[nb], gacc[p]);
+      }
+#pragma unroll
+      for (int p = 0; p < NG; ++p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gd[p][q] += (double)gacc[p][q];
+        gacc[p] = f4{0, 0, 0, 0};
+      }
+    }
+  };
+
+  for (; tile < ntiles; tile += 2 * nwg) {
+    body(tile, pf0, ok0);
+    if (tile + nwg < ntiles) body(tile + nwg, pf1, ok1);
+  }
+
+  // ---- per-workgroup outputs
+  if (MODE == 3) return;
+  const int wg = blockIdx.x;
+  if (want_norm) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsum += __shfl_xor(nsum, off, 64);
+    if (lane == 0) a.norm2_parts[wg * NW + w] = nsum;
+  }
+  float* lp = a.lacc_parts + (int64_t)wg * I * R;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int m = w + NW * rt;
+    if (m < MT) {
+#pragma unroll
+      for (int n = 0; n < NR; ++n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * m + 4 * lk + q, r = 16 * n + lr;
+          if (i < I && r < R) lp[i * R + r] = lacc[rt][n][q];
+        }
+      }
+    }
+  }
+  if (MODE == 0) {
+    double* gp = a.gv_parts + (int64_t)(wg * NW + w) * R * R;
+    int p = 0;
+#pragma unroll
+    for (int na = 0; na < NR; ++na) {
+#pragma unroll
+      for (int nb = na; nb < NR; ++nb, ++p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * na + 4 * lk + q, col = 16 * nb + lr;
+          if (row < R && col < R) {
+            gp[row * R + col] = gd[p][q];
+            gp[col * R + row] = gd[p][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NR, int MODE, int IC>
+void launch3(const FusedArgs& a, int nwg, hipStream_t s) {
+  const size_t bytes = (size_t)lds_b16((int)a.v.I, NR, MODE).total;
+  (void)hipFuncSetAttribute((const void*)k_fused_bf16<NR, MODE, IC>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipLaunchKernelGGL((k_fused_bf16<NR, MODE, IC>), dim3(nwg), dim3(NT), bytes, s, a);
+}
+
+template <int NR, int MODE>
+void launch2(const FusedArgs& a, int nwg, hipStream_t s) {
+  if (a.v.I <= 64) launch3<NR, MODE, 8>(a, nwg, s);
+  else if (a.v.I <= 128) launch3<NR, MODE, 16>(a, nwg, s);
+  else launch3<NR, MODE, 32>(a, nwg, s);
+}
+
+template <int NR>
+void launch1(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
+  if (mode == 0) launch2<NR, 0>(a, nwg, s);
+  else if (mode == 2) launch2<NR, 2>(a, nwg, s);
+  else launch2<NR, 3>(a, nwg, s);
+}
+
+}  // namespace
+
+constexpr int LDS_MAX_BYTES_B16 = 160 * 1024;
+
+bool fused_bf16_supported(const FusedArgs& a, int mode) {
+  const View& v = a.v;
+  if (a.x_dtype != TK_BF16 || mode == 1) return false;
+  if (v.Q < 2 || (v.Q & 1) || ((uintptr_t)a.X & 3)) return false;
+  if (v.I < 1 || v.I > 256 || a.R < 1 || a.R > 48) return false;
+  const int NR = (a.R + 15) / 16;
+  return (size_t)lds_b16((int)v.I, NR, mode).total <= (size_t)LDS_MAX_BYTES_B16;
+}
+
+int launch_fused_bf16(const FusedArgs& a, int mode, int nwg_max, hipStream_t s) {
+  int64_t ntiles = ceil_div(a.v.J(), TJ);
+  int nwg = (int)(ntiles < NWG ? ntiles : NWG);
+  if (nwg > nwg_max / NW) nwg = nwg_max / NW;
+  switch ((a.R + 15) / 16) {
+    case 1: launch1<1>(a, mode, nwg, s); break;
+    case 2: launch1<2>(a, mode, nwg, s); break;
+    case 3: launch1<3>(a, mode, nwg, s); break;
+  }
+  return nwg;
+}
+
+}  // namespace tk

@@ -102,6 +102,10 @@ bool fused_ttm_supported(int x_dtype, const View& v, int64_t J);
 // [W][I][R], Gram and residual partials [FUSED_WAVES * W] (one per wave).
 constexpr int FUSED_WAVES = 8;
 int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
+// BF16 storage on the BF16 matrix cores (sweep, init, TTM; Q even): used by
+// launch_fused when it takes the shape; same partial-buffer layout.
+bool fused_bf16_supported(const FusedArgs& a, int mode);
+int launch_fused_bf16(const FusedArgs& a, int mode, int nwg_max, hipStream_t s);
 
 // One-workgroup FP64 steps of the mode solve (see k_mode_step.hip).
 enum { STEP_SOLVE = 1, STEP_QR = 2, STEP_PREP = 4, STEP_PREP_SPECULATIVE = 8 };
