@@ -403,7 +403,8 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     }
   }
   if (MODE != 2) {
-    // the upper block triangle and its mirror cover every entry
+    // the upper triangle (of the diagonal blocks too) and its mirror cover
+    // every entry once, so each partial is exactly symmetric
     double* gp = a.gv_parts + (int64_t)(wg * NW + w) * R * R;
     int p = 0;
 #pragma unroll
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int row = 16 * na + 4 * lk + q, col = 16 * nb + lr;
-          if (row < R && col < R) {
+          if (row < R && col < R && (na < nb || row <= col)) {
             gp[row * R + col] = gd[p][q];
             gp[col * R + row] = gd[p][q];
           }

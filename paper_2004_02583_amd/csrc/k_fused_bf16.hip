@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int row = 16 * na + 4 * lk + q, col = 16 * nb + lr;
-          if (row < R && col < R) {
+          if (row < R && col < R && (na < nb || row <= col)) {
             gp[row * R + col] = gd[p][q];
             gp[col * R + row] = gd[p][q];
           }
@@ -365,6 +365,305 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Variant for R <= 32 (NR = 1, 2) and 32 * ceil(I / 32) <= 224: wave w owns
+// rank tile n = w % NR and the fibre blocks w / NR + (8 / NR) b, b < NR, so
+// its three Lq^T splits (the R-update B operands of every 32-row stage)
+// stay in registers for the whole launch; G_V comes from the V splits on
+// the BF16 matrix cores (the six products h h, h m, m h, h l, l h, m m: the
+// three dropped ones are below FP32 rounding); and the tile is double
+// buffered in LDS, so the stash of the next tile overlaps this tile's
+// R-update.  Two barriers per tile.
+
+constexpr int XR_MAX_R = 224;
+
+__host__ __device__ inline LdsB lds_b16r(int I, int NR, int mode) {
+  const int RP = 16 * NR;
+  const int XR = 32 * ((I + 31) / 32);
+  LdsB l;
+  l.xs = 0;
+  l.lq = 2 * (XR + 1) * XS * 2;            // end of the two tile buffers
+  l.vt = l.lq;
+  l.vf = l.vt + (mode != 3 ? 3 * RP * VS * 2 : 0);
+  l.total = l.vf + (mode == 3 ? RP * (TJ + 1) * 4 : 0);
+  return l;
+}
+
+template <int NR, int MODE, int IC>
+__global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  constexpr int RP = 16 * NR;
+  constexpr int NG = NR * (NR + 1) / 2;
+  constexpr int RT = IC == 32 ? 2 : 1;        // L-update row tiles per wave
+  // row slots per wave and 32-row stages for 32 ceil(I / 32) <= 224
+  constexpr int ICR = IC == 32 ? XR_MAX_R / NW : IC;
+  constexpr int STM = ICR / 4;
+  const View v = a.v;
+  const int I = (int)v.I, R = a.R;
+  const int64_t J = v.J();
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int XR = 32 * ((I + 31) / 32);
+  const int MT = (I + 15) / 16;
+  const int ST = XR / 32;
+  const int nw = w % NR;                      // rank tile of this wave (R-update)
+  const LdsB L = lds_b16r(I, NR, MODE);
+  const int xbuf = (XR + 1) * XS;             // elements per tile buffer
+  __bf16* Xs = (__bf16*)(smem + L.xs);
+  uint32_t* Xs32 = (uint32_t*)(smem + L.xs);
+  __bf16* Vt = (__bf16*)(smem + L.vt);        // [3][RP][VS]
+  float* Vf = (float*)(smem + L.vf);          // TTM: [RP][TJ + 1]
+
+  for (int e = threadIdx.x; e < xbuf; e += NT) Xs32[e] = 0u;   // both buffers
+
+  // Lq^T splits of rank 16 nw + lr, rows 32 st + 8 lk + e, as B operands
+  bf8 bq[STM][3];
+  if (MODE != 2) {
+    const int64_t ldi = a.lq_ldi ? a.lq_ldi : R, ldo = a.lq_ldi ? a.lq_ldo : 1;
+    const int r = 16 * nw + lr;
+#pragma unroll
+    for (int st = 0; st < STM; ++st) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int row = 32 * st + 8 * lk + e;
+        const float x = (row < I && r < R) ? a.Lq[row * ldi + r * ldo] : 0.0f;
+        __bf16 h, m, l;
+        split3(x, h, m, l);
+        bq[st][0][e] = h;
+        bq[st][1][e] = m;
+        bq[st][2][e] = l;
+      }
+    }
+  }
+
+  f4 lacc[RT][NR];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int n = 0; n < NR; ++n) lacc[rt][n] = f4{0, 0, 0, 0};
+  f4 gacc[NG];
+  double gd[NG][4];
+#pragma unroll
+  for (int p = 0; p < NG; ++p) {
+    gacc[p] = f4{0, 0, 0, 0};
+    gd[p][0] = gd[p][1] = gd[p][2] = gd[p][3] = 0.0;
+  }
+  double nsum = 0.0;
+  const bool want_norm = MODE == 2 && a.norm2_parts != nullptr;
+
+  const uint32_t* X2 = (const uint32_t*)a.X;
+  const int64_t ntiles = ceil_div(J, TJ);
+  const int nwg = gridDim.x;
+  uint32_t pf[ICR];
+  bool pf_ok = false;
+  int64_t tile = blockIdx.x;
+  int cur = 0;
+  __syncthreads();
+  if (tile < ntiles) {
+    prefetch<ICR>(X2, v, tile * TJ, lane, w, pf, pf_ok);
+    if (want_norm) stash<ICR, true>(v, lane, w, pf, pf_ok, XR, Xs32, nsum);
+    else stash<ICR, false>(v, lane, w, pf, pf_ok, XR, Xs32, nsum);
+    if (tile + nwg < ntiles) prefetch<ICR>(X2, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
+  }
+  __syncthreads();
+
+  for (; tile < ntiles; tile += nwg, cur ^= 1) {
+    const int64_t j0 = tile * TJ;
+    const __bf16* Xc = Xs + cur * xbuf;
+
+    // ---- phase A: R-update (or sketch rows) of this tile; stash the next
+    if (MODE != 2) {
+      f4 vacc[NR];
+#pragma unroll
+      for (int b = 0; b < NR; ++b) vacc[b] = f4{0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < STM; ++st) {
+        if (st < ST) {
+          const int row0 = 32 * st + 8 * lk;
+#pragma unroll
+          for (int b = 0; b < NR; ++b) {
+            const int f = 16 * (w / NR + (NW / NR) * b) + lr;
+            const __bf16* xc = Xc + xidx(row0, f);
+            bf8 av;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
+#pragma unroll
+            for (int s3 = 0; s3 < 3; ++s3) vacc[b] = mfma_bf16(av, bq[st][s3], vacc[b]);
+          }
+        }
+      }
+      // V[16 fb + 4 lk + q][16 nw + lr] = vacc[b][q]
+#pragma unroll
+      for (int b = 0; b < NR; ++b) {
+        const int fq = 16 * (w / NR + (NW / NR) * b) + 4 * lk;
+        if (MODE == 3) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Vf[(16 * nw + lr) * (TJ + 1) + fq + q] = vacc[b][q];
+        } else {
+          bf16_t hs[4], ms[4], ls[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            __bf16 h, m, l;
+            split3(vacc[b][q], h, m, l);
+            hs[q] = __builtin_bit_cast(bf16_t, h);
+            ms[q] = __builtin_bit_cast(bf16_t, m);
+            ls[q] = __builtin_bit_cast(bf16_t, l);
+          }
+          const int o = (16 * nw + lr) * VS + fq;          // 8-byte aligned
+          uint2* d0 = (uint2*)(Vt + 0 * RP * VS + o);
+          uint2* d1 = (uint2*)(Vt + 1 * RP * VS + o);
+          uint2* d2 = (uint2*)(Vt + 2 * RP * VS + o);
+          *d0 = make_uint2(hs[0] | ((uint32_t)hs[1] << 16), hs[2] | ((uint32_t)hs[3] << 16));
+          *d1 = make_uint2(ms[0] | ((uint32_t)ms[1] << 16), ms[2] | ((uint32_t)ms[3] << 16));
+          *d2 = make_uint2(ls[0] | ((uint32_t)ls[1] << 16), ls[2] | ((uint32_t)ls[3] << 16));
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < TJ * RP; e += NT) {
+        const int jl = e / RP, r = e - (e / RP) * RP;
+        const int64_t j = j0 + jl;
+        float sv = 0.0f;
+        if (j < J && r < R)
+          sv = sketch_value(a.seed, ((uint64_t)a.mode << 48) + (uint64_t)(j * R + r));
+        __bf16 h, m, l;
+        split3(sv, h, m, l);
+        Vt[(0 * RP + r) * VS + jl] = h;
+        Vt[(1 * RP + r) * VS + jl] = m;
+        Vt[(2 * RP + r) * VS + jl] = l;
+      }
+    }
+    if (tile + nwg < ntiles) {
+      uint32_t* Xn32 = Xs32 + (cur ^ 1) * (xbuf >> 1);
+      if (want_norm) stash<ICR, true>(v, lane, w, pf, pf_ok, XR, Xn32, nsum);
+      else stash<ICR, false>(v, lane, w, pf, pf_ok, XR, Xn32, nsum);
+      if (tile + 2 * nwg < ntiles)
+        prefetch<ICR>(X2, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
+    }
+    __syncthreads();
+
+    // ---- phase B
+    if (MODE == 3) {
+      float* Y = a.y;
+      for (int half = 0; half < 2; ++half) {
+        const int jl = lane + 64 * half;
+        const int64_t j = j0 + jl;
+        if (j < J) {
+          const int64_t p = j / v.Q, q = j - p * v.Q;
+          float* yb = Y + p * (int64_t)R * v.Q + q;
+          for (int r = w; r < R; r += NW) yb[(int64_t)r * v.Q] = Vf[r * (TJ + 1) + jl];
+        }
+      }
+    } else {
+      // L-update: row tiles m = w + 8 rt (clamped; duplicates never stored)
+      int rowm[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) rowm[rt] = 16 * min(w + NW * rt, MT - 1) + lr;
+#pragma unroll
+      for (int ks = 0; ks < TJ / 32; ++ks) {
+        bf8 av[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) av[rt] = *(const bf8*)(Xc + xidx(rowm[rt], 32 * ks + 8 * lk));
+#pragma unroll
+        for (int n = 0; n < NR; ++n) {
+#pragma unroll
+          for (int s3 = 0; s3 < 3; ++s3) {
+            const bf8 bv = *(const bf8*)(Vt + (s3 * RP + 16 * n + lr) * VS + 32 * ks + 8 * lk);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) lacc[rt][n] = mfma_bf16(av[rt], bv, lacc[rt][n]);
+          }
+        }
+      }
+      if (MODE == 0) {
+        // G_V block pair p = (na, nb), K step ks: unit 4 p + ks goes to wave
+        // (4 p + ks) % 8; six split products each.
+        int p = 0;
+#pragma unroll
+        for (int na = 0; na < NR; ++na) {
+#pragma unroll
+          for (int nb = na; nb < NR; ++nb, ++p) {
+#pragma unroll
+            for (int ks = 0; ks < TJ / 32; ++ks) {
+              if (((4 * p + ks) & (NW - 1)) == w) {
+                const int ko = 32 * ks + 8 * lk;
+                const bf8 ah = *(const bf8*)(Vt + (0 * RP + 16 * na + lr) * VS + ko);
+                const bf8 am = *(const bf8*)(Vt + (1 * RP + 16 * na + lr) * VS + ko);
+                const bf8 al = *(const bf8*)(Vt + (2 * RP + 16 * na + lr) * VS + ko);
+                const bf8 bh = *(const bf8*)(Vt + (0 * RP + 16 * nb + lr) * VS + ko);
+                const bf8 bm = *(const bf8*)(Vt + (1 * RP + 16 * nb + lr) * VS + ko);
+                const bf8 bl = *(const bf8*)(Vt + (2 * RP + 16 * nb + lr) * VS + ko);
+                gacc[p] = mfma_bf16(ah, bh, gacc[p]);
+                gacc[p] = mfma_bf16(ah, bm, gacc[p]);
+                gacc[p] = mfma_bf16(am, bh, gacc[p]);
+                gacc[p] = mfma_bf16(ah, bl, gacc[p]);
+                gacc[p] = mfma_bf16(al, bh, gacc[p]);
+                gacc[p] = mfma_bf16(am, bm, gacc[p]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < NG; ++q2) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) gd[q2][q] += (double)gacc[q2][q];
+          gacc[q2] = f4{0, 0, 0, 0};
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- per-workgroup outputs
+  if (MODE == 3) return;
+  const int wg = blockIdx.x;
+  if (want_norm) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsum += __shfl_xor(nsum, off, 64);
+    if (lane == 0) a.norm2_parts[wg * NW + w] = nsum;
+  }
+  float* lp = a.lacc_parts + (int64_t)wg * I * R;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int m = w + NW * rt;
+    if (m < MT) {
+#pragma unroll
+      for (int n = 0; n < NR; ++n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * m + 4 * lk + q, r = 16 * n + lr;
+          if (i < I && r < R) lp[i * R + r] = lacc[rt][n][q];
+        }
+      }
+    }
+  }
+  if (MODE == 0) {
+    double* gp = a.gv_parts + (int64_t)(wg * NW + w) * R * R;
+    int p = 0;
+#pragma unroll
+    for (int na = 0; na < NR; ++na) {
+#pragma unroll
+      for (int nb = na; nb < NR; ++nb, ++p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * na + 4 * lk + q, col = 16 * nb + lr;
+          if (row < R && col < R && (na < nb || row <= col)) {
+            gp[row * R + col] = gd[p][q];
+            gp[col * R + row] = gd[p][q];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NR, int MODE, int IC>
+void launch3r(const FusedArgs& a, int nwg, hipStream_t s) {
+  const size_t bytes = (size_t)lds_b16r((int)a.v.I, NR, MODE).total;
+  (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC>), dim3(nwg), dim3(NT), bytes, s, a);
 }
 
 template <int NR, int MODE, int IC>
@@ -377,6 +676,12 @@ void launch3(const FusedArgs& a, int nwg, hipStream_t s) {
 
 template <int NR, int MODE>
 void launch2(const FusedArgs& a, int nwg, hipStream_t s) {
+  if (NR <= 2 && 32 * ((a.v.I + 31) / 32) <= XR_MAX_R) {
+    if (a.v.I <= 64) launch3r<NR <= 2 ? NR : 2, MODE, 8>(a, nwg, s);
+    else if (a.v.I <= 128) launch3r<NR <= 2 ? NR : 2, MODE, 16>(a, nwg, s);
+    else launch3r<NR <= 2 ? NR : 2, MODE, 32>(a, nwg, s);
+    return;
+  }
   if (a.v.I <= 64) launch3<NR, MODE, 8>(a, nwg, s);
   else if (a.v.I <= 128) launch3<NR, MODE, 16>(a, nwg, s);
   else launch3<NR, MODE, 32>(a, nwg, s);
@@ -399,6 +704,8 @@ bool fused_bf16_supported(const FusedArgs& a, int mode) {
   if (v.Q < 2 || (v.Q & 1) || ((uintptr_t)a.X & 3)) return false;
   if (v.I < 1 || v.I > 256 || a.R < 1 || a.R > 48) return false;
   const int NR = (a.R + 15) / 16;
+  if (NR <= 2 && 32 * ((v.I + 31) / 32) <= XR_MAX_R)
+    return (size_t)lds_b16r((int)v.I, NR, mode).total <= (size_t)LDS_MAX_BYTES_B16;
   return (size_t)lds_b16((int)v.I, NR, mode).total <= (size_t)LDS_MAX_BYTES_B16;
 }
 

@@ -23,20 +23,36 @@
 namespace tk {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 1024;
 constexpr int LD = 65;     // LDS row stride of the r x r matrices
-constexpr int TR = 32;     // rows per staged Gram tile
+constexpr int TR = 64;     // rows per staged tile
+constexpr int PPT = 3;     // Gram pairs per thread (r (r + 1) / 2 <= 2080 <= 3 NT)
+
+// sum_{l < n} x[l * sx] * y[l * sy] with four independent partial sums
+// (combined in a fixed order).
+__device__ __forceinline__ double dot4(const double* x, int sx, const double* y, int sy, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int l = 0;
+  for (; l + 3 < n; l += 4) {
+    s0 += x[l * sx] * y[l * sy];
+    s1 += x[(l + 1) * sx] * y[(l + 1) * sy];
+    s2 += x[(l + 2) * sx] * y[(l + 2) * sy];
+    s3 += x[(l + 3) * sx] * y[(l + 3) * sy];
+  }
+  for (; l < n; ++l) s0 += x[l * sx] * y[l * sy];
+  return (s0 + s1) + (s2 + s3);
+}
 
 // G = X^T X (r x r, LDS, stride LD) of the m x r matrix X (type T, global):
-// thread t owns the upper-triangle pairs t, t + NT, ... (at most 9 for r = 64).
+// thread t owns the upper-triangle pairs t, t + NT, ... (at most PPT).
 template <typename T>
 __device__ void bgram(const T* __restrict__ X, int64_t m, int r, double* G, double* tile) {
   const int npair = r * (r + 1) / 2;
-  double acc[9];
-  int pa[9], pb[9];
+  double acc[PPT];
+  int pa[PPT], pb[PPT];
   int cnt = 0;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < PPT; ++c) {
     const int t = (int)threadIdx.x + NT * c;
     int a = 0, rem = t < npair ? t : 0;
     while (rem >= r - a) { rem -= r - a; ++a; }
@@ -52,16 +68,11 @@ __device__ void bgram(const T* __restrict__ X, int64_t m, int r, double* G, doub
       tile[e] = (double)Elem<T>::load(X + i0 * r + e);
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      if (c < cnt) {
-        double s = 0.0;
-        for (int i = 0; i < rows; ++i) s += tile[i * r + pa[c]] * tile[i * r + pb[c]];
-        acc[c] += s;
-      }
-    }
+    for (int c = 0; c < PPT; ++c)
+      if (c < cnt) acc[c] += dot4(tile + pa[c], r, tile + pb[c], r, rows);
   }
 #pragma unroll
-  for (int c = 0; c < 9; ++c) {
+  for (int c = 0; c < PPT; ++c) {
     if (c < cnt) {
       G[pa[c] * LD + pb[c]] = acc[c];
       G[pb[c] * LD + pa[c]] = acc[c];
@@ -114,8 +125,7 @@ __device__ void binv(const double* C, int r, double* W) {
   if (j < r) {
     for (int k = 0; k < j; ++k) W[k * LD + j] = 0.0;
     for (int k = j; k < r; ++k) {
-      double v = (k == j) ? 1.0 : 0.0;
-      for (int l = j; l < k; ++l) v -= C[k * LD + l] * W[l * LD + j];
+      const double v = ((k == j) ? 1.0 : 0.0) - dot4(C + k * LD + j, 1, W + j * LD + j, LD, k - j);
       W[k * LD + j] = v / C[k * LD + k];
     }
   }
@@ -126,29 +136,28 @@ __device__ void binv(const double* C, int r, double* W) {
 __device__ void bwtw(const double* W, int r, double* M) {
   for (int e = threadIdx.x; e < r * r; e += NT) {
     const int a = e / r, b = e % r;
-    double s = 0.0;
-    for (int k = a > b ? a : b; k < r; ++k) s += W[k * LD + a] * W[k * LD + b];
-    M[a * LD + b] = s;
+    const int k0 = a > b ? a : b;
+    M[a * LD + b] = dot4(W + k0 * LD + a, LD, W + k0 * LD + b, LD, r - k0);
   }
   __syncthreads();
 }
 
 // X = B W (trans = 0) or X = B W^T (trans = 1) with W r x r in LDS; B is
-// m x r FP64 (global), X has element type TO.  One output element per
-// thread and step, r products each.
+// m x r FP64 (global, staged through LDS TR rows at a time), X has element
+// type TO.  One output element per thread and step, r products each.
 template <typename TO>
 __device__ void bapply(const double* __restrict__ B, int64_t m, int r, const double* W,
-                       int trans, TO* __restrict__ X) {
-  const int64_t n = m * r;
+                       int trans, TO* __restrict__ X, double* tile) {
   const int si = trans ? LD : 1, sl = trans ? 1 : LD;
-  for (int64_t e = threadIdx.x; e < n; e += NT) {
-    const int64_t i = e / r;
-    const int k = (int)(e - i * r);
-    const double* b = B + i * r;
-    const double* w = W + k * si;
-    double s = 0.0;
-    for (int l = 0; l < r; ++l) s += b[l] * w[l * sl];
-    X[e] = Store<TO>::cvt(s);
+  for (int64_t i0 = 0; i0 < m; i0 += TR) {
+    const int rows = (int)((m - i0) < TR ? (m - i0) : TR);
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * r; e += NT) tile[e] = B[i0 * r + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * r; e += NT) {
+      const int ii = e / r, k = e - ii * r;
+      X[i0 * r + e] = Store<TO>::cvt(dot4(tile + ii * r, 1, W + k * si, sl, r));
+    }
   }
   __syncthreads();
 }
@@ -182,8 +191,7 @@ __global__ void __launch_bounds__(NT) k_mode_step(StepArgs a) {
     const int col = threadIdx.x;
     if (col < r) {
       for (int k = col; k < r; ++k) {
-        double v = A1[k * LD + col];
-        for (int l = col; l < k; ++l) v -= A2[k * LD + l] * A1[l * LD + col];
+        double v = A1[k * LD + col] - dot4(A2 + k * LD + col, 1, A1 + col * LD + col, LD, k - col);
         v /= A2[k * LD + k];
         A1[k * LD + col] = v;
         s += v * v;
@@ -199,7 +207,7 @@ __global__ void __launch_bounds__(NT) k_mode_step(StepArgs a) {
     }
     // L_{k+1} = L_acc (D D^T)^{-1}
     bwtw(W, r, A1);
-    bapply<double>(a.Lacc, m, r, A1, 0, a.Lnext);
+    bapply<double>(a.Lacc, m, r, A1, 0, a.Lnext, tile);
     src = a.Lnext;
   }
 
@@ -211,14 +219,14 @@ __global__ void __launch_bounds__(NT) k_mode_step(StepArgs a) {
       return;
     }
     binv(A1, r, W);
-    bapply<double>(a.Qin, m, r, W, 1, a.Q1);
+    bapply<double>(a.Qin, m, r, W, 1, a.Q1, tile);
     bgram<double>(a.Q1, m, r, A1, tile);
     if (bchol(A1, r, &flag, &dmax)) {
       if (threadIdx.x == 0) *a.status = TK_ERR_RANK_DEFICIENT;
       return;
     }
     binv(A1, r, W);
-    bapply<double>(a.Q1, m, r, W, 1, a.Qout);
+    bapply<double>(a.Q1, m, r, W, 1, a.Qout, tile);
     src = a.Qout;
   }
 
@@ -232,7 +240,7 @@ __global__ void __launch_bounds__(NT) k_mode_step(StepArgs a) {
     binv(A1, r, W);
     bwtw(W, r, A1);
     TQ* Lq = (TQ*)a.Lq;
-    bapply<TQ>(src, m, r, A1, 0, Lq);
+    bapply<TQ>(src, m, r, A1, 0, Lq, tile);
     if (a.Lr) {
       TQ* Lr = (TQ*)a.Lr;
       for (int64_t e = threadIdx.x; e < m * r; e += NT) Lr[e] = Store<TQ>::cvt(src[e]);
