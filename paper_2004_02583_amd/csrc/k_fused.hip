@@ -476,6 +476,7 @@ constexpr int LDS_MAX_BYTES = 160 * 1024;
 
 bool fused_supported(int x_dtype, const View& v, int R, int resid_mode) {
   if (x_dtype != TK_F32 && x_dtype != TK_BF16) return false;
+  if (fused_big_shape(x_dtype, v, R, resid_mode == TK_RESID_EXPLICIT ? 1 : 0)) return true;
   if (v.I > 256 || v.I < 1 || R < 1 || R > 48) return false;
   const int NR = (R + 15) / 16;
   const int mode = resid_mode == TK_RESID_EXPLICIT ? 1 : 0;
@@ -484,6 +485,7 @@ bool fused_supported(int x_dtype, const View& v, int R, int resid_mode) {
 
 bool fused_ttm_supported(int x_dtype, const View& v, int64_t J) {
   if (x_dtype != TK_F32 && x_dtype != TK_BF16) return false;
+  if (fused_big_shape(x_dtype, v, J, 3)) return true;
   if (v.I > 256 || v.I < 1 || J < 1 || J > 48) return false;
   const int NR = (int)((J + 15) / 16);
   return (size_t)lds_layout((int)v.I, NR, 3).total * 4 <= (size_t)LDS_MAX_BYTES;
@@ -498,6 +500,7 @@ int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s) {
   int nwg = fused_workgroups(a.v);
   if (nwg > nwg_max / NW) nwg = nwg_max / NW;
   const int mode = a.y ? 3 : a.sketch ? 2 : (a.Lr ? 1 : 0);
+  if (fused_big_shape(a.x_dtype, a.v, a.R, mode)) return launch_fused_big(a, mode, nwg_max, s);
   if (fused_bf16_supported(a, mode)) return launch_fused_bf16(a, mode, nwg_max, s);
   if (a.x_dtype == TK_F32) return launch_t<float>(a, mode, nwg, s);
   return launch_t<bf16_t>(a, mode, nwg, s);

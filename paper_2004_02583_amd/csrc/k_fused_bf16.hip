@@ -379,9 +379,13 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
 
 constexpr int XR_MAX_R = 224;
 
-__host__ __device__ inline LdsB lds_b16r(int I, int NR, int mode) {
+// Tile rows of the size class: 64, 128 or 224 (I <= 64, 128, 224), the
+// rows past I zero, so the R-update runs a fixed number of 32-row stages.
+__host__ __device__ constexpr int xrows_r(int IC) { return IC == 32 ? XR_MAX_R : 4 * 8 * (IC / 4); }
+
+__host__ __device__ inline LdsB lds_b16r(int IC, int NR, int mode) {
   const int RP = 16 * NR;
-  const int XR = 32 * ((I + 31) / 32);
+  const int XR = xrows_r(IC);
   LdsB l;
   l.xs = 0;
   l.lq = 2 * (XR + 1) * XS * 2;            // end of the two tile buffers
@@ -397,20 +401,19 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   constexpr int RP = 16 * NR;
   constexpr int NG = NR * (NR + 1) / 2;
   constexpr int RT = IC == 32 ? 2 : 1;        // L-update row tiles per wave
-  // row slots per wave and 32-row stages for 32 ceil(I / 32) <= 224
-  constexpr int ICR = IC == 32 ? XR_MAX_R / NW : IC;
-  constexpr int STM = ICR / 4;
+  // row slots per wave and 32-row stages of the size class
+  constexpr int XR = xrows_r(IC);
+  constexpr int ICR = XR / NW;
+  constexpr int STM = XR / 32;
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const int XR = 32 * ((I + 31) / 32);
   const int MT = (I + 15) / 16;
-  const int ST = XR / 32;
   const int nw = w % NR;                      // rank tile of this wave (R-update)
-  const LdsB L = lds_b16r(I, NR, MODE);
+  const LdsB L = lds_b16r(IC, NR, MODE);
   const int xbuf = (XR + 1) * XS;             // elements per tile buffer
   __bf16* Xs = (__bf16*)(smem + L.xs);
   uint32_t* Xs32 = (uint32_t*)(smem + L.xs);
@@ -481,18 +484,16 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
       for (int b = 0; b < NR; ++b) vacc[b] = f4{0, 0, 0, 0};
 #pragma unroll
       for (int st = 0; st < STM; ++st) {
-        if (st < ST) {
-          const int row0 = 32 * st + 8 * lk;
+        const int row0 = 32 * st + 8 * lk;
 #pragma unroll
-          for (int b = 0; b < NR; ++b) {
-            const int f = 16 * (w / NR + (NW / NR) * b) + lr;
-            const __bf16* xc = Xc + xidx(row0, f);
-            bf8 av;
+        for (int b = 0; b < NR; ++b) {
+          const int f = 16 * (w / NR + (NW / NR) * b) + lr;
+          const __bf16* xc = Xc + xidx(row0, f);
+          bf8 av;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
+          for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
 #pragma unroll
-            for (int s3 = 0; s3 < 3; ++s3) vacc[b] = mfma_bf16(av, bq[st][s3], vacc[b]);
-          }
+          for (int s3 = 0; s3 < 3; ++s3) vacc[b] = mfma_bf16(av, bq[st][s3], vacc[b]);
         }
       }
       // V[16 fb + 4 lk + q][16 nw + lr] = vacc[b][q]
@@ -660,7 +661,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
 
 template <int NR, int MODE, int IC>
 void launch3r(const FusedArgs& a, int nwg, hipStream_t s) {
-  const size_t bytes = (size_t)lds_b16r((int)a.v.I, NR, MODE).total;
+  const size_t bytes = (size_t)lds_b16r(IC, NR, MODE).total;
   (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC>), dim3(nwg), dim3(NT), bytes, s, a);
@@ -676,7 +677,7 @@ void launch3(const FusedArgs& a, int nwg, hipStream_t s) {
 
 template <int NR, int MODE>
 void launch2(const FusedArgs& a, int nwg, hipStream_t s) {
-  if (NR <= 2 && 32 * ((a.v.I + 31) / 32) <= XR_MAX_R) {
+  if (NR <= 2 && a.v.I <= XR_MAX_R) {
     if (a.v.I <= 64) launch3r<NR <= 2 ? NR : 2, MODE, 8>(a, nwg, s);
     else if (a.v.I <= 128) launch3r<NR <= 2 ? NR : 2, MODE, 16>(a, nwg, s);
     else launch3r<NR <= 2 ? NR : 2, MODE, 32>(a, nwg, s);
@@ -704,8 +705,9 @@ bool fused_bf16_supported(const FusedArgs& a, int mode) {
   if (v.Q < 2 || (v.Q & 1) || ((uintptr_t)a.X & 3)) return false;
   if (v.I < 1 || v.I > 256 || a.R < 1 || a.R > 48) return false;
   const int NR = (a.R + 15) / 16;
-  if (NR <= 2 && 32 * ((v.I + 31) / 32) <= XR_MAX_R)
-    return (size_t)lds_b16r((int)v.I, NR, mode).total <= (size_t)LDS_MAX_BYTES_B16;
+  if (NR <= 2 && v.I <= XR_MAX_R)
+    return (size_t)lds_b16r(v.I <= 64 ? 8 : v.I <= 128 ? 16 : 32, NR, mode).total <=
+           (size_t)LDS_MAX_BYTES_B16;
   return (size_t)lds_b16((int)v.I, NR, mode).total <= (size_t)LDS_MAX_BYTES_B16;
 }
 

@@ -106,6 +106,10 @@ int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
 // launch_fused when it takes the shape; same partial-buffer layout.
 bool fused_bf16_supported(const FusedArgs& a, int mode);
 int launch_fused_bf16(const FusedArgs& a, int mode, int nwg_max, hipStream_t s);
+// Modes of 256 < I <= 1024 rows (R <= 48; sweep, init, TTM), streamed in
+// chunks of rows: used by launch_fused when it takes the shape.
+bool fused_big_shape(int x_dtype, const View& v, int64_t R, int mode);
+int launch_fused_big(const FusedArgs& a, int mode, int nwg_max, hipStream_t s);
 
 // One-workgroup FP64 steps of the mode solve (see k_mode_step.hip).
 enum { STEP_SOLVE = 1, STEP_QR = 2, STEP_PREP = 4, STEP_PREP_SPECULATIVE = 8 };

@@ -51,6 +51,8 @@ TTM_CASES = [
     ((65, 129), 0, 70, False),      # order 2, more outputs than one chunk
     ((300, 150), 1, 37, True),      # Q == 1, 48-wide rank padding, ragged fibre tiles
     ((33, 256, 17), 1, 48, False),  # largest mode and output width of the MFMA TTM
+    ((40, 520, 9), 1, 48, True),    # large-mode TTM (chunked rows)
+    ((33, 700), 1, 20, False),      # large-mode TTM, Q == 1
 ]
 
 
@@ -291,7 +293,10 @@ KERNEL_CASES = [
     ((17, 33, 65), 1, 3),       # R not a multiple of 4, ragged everything
     ((64, 256, 9), 1, 32),      # I = 256, R = 32
     ((9, 100, 70), 1, 48),      # R = 48 (largest fused rank)
-    ((300, 20, 40), 0, 12),     # I > 256: two-pass kernels
+    ((300, 20, 40), 0, 12),     # I > 256: chunked large-mode kernel
+    ((7, 600, 33), 1, 40),      # I = 600: ragged last chunk, tiles straddle p
+    ((50, 1024), 1, 48),        # I = 1024, Q == 1, R = 48, one ragged tile
+    ((1100, 8, 9), 0, 5),       # I > 1024: generic two-pass kernels
 ]
 
 
@@ -320,11 +325,27 @@ def test_sweep_kernel_parity(gpu_lib, dims, mode, R, dt):
     np.testing.assert_array_equal(np64(GV), np64(GV).T)
 
 
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("which", ["t", "st"])
+def test_large_mode_driver_parity(gpu_lib, which, dt):
+    """A 700-row mode runs the chunked large-mode kernels (sketch, sweeps, TTM)."""
+    tk = gpu_lib
+    flush(f"large-mode driver {which} {dt}")
+    rng = np.random.default_rng(42)
+    A = synth.tucker_lowrank(rng, (700, 24, 30), (20, 6, 8), 1e-3)[0]
+    Ah = held(A, dt)
+    run = tk.als_thosvd if which == "t" else tk.als_sthosvd
+    G, Us, info = run(to_gpu(A, dt), (20, 6, 8), tol=1e-5, seed=3)
+    ref = (o.thosvd_als if which == "t" else o.sthosvd_als)(Ah, (20, 6, 8), tol=1e-5, seed=3)
+    gate = 1e-5 if dt == "f32" else 1e-2
+    assert abs(_relerr_of(Ah, G, Us) - o.relerr(Ah, ref.G, ref.U)) <= gate
+
+
 def test_two_pass_driver_parity(gpu_lib):
-    """I_1 = 300 > 256 runs the two-pass kernels for mode 1."""
+    """I_1 = 1100 > 1024 runs the generic two-pass kernels for mode 1."""
     tk = gpu_lib
     rng = np.random.default_rng(41)
-    A = synth.tucker_lowrank(rng, (300, 24, 20), (10, 6, 8), 1e-3)[0]
+    A = synth.tucker_lowrank(rng, (1100, 24, 20), (10, 6, 8), 1e-3)[0]
     Ah = held(A, "f32")
     G, Us, info = tk.als_sthosvd(to_gpu(A, "f32"), (10, 6, 8), tol=1e-6, seed=5)
     ref = o.sthosvd_als(Ah, (10, 6, 8), tol=1e-6, seed=5)
