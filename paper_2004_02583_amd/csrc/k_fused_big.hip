@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_big(FusedArgs a) {
 #pragma unroll
           for (int ks = 0; ks < 16; ++ks) acc = mfma16(xa[4 * ks * XLD], lb[4 * ks * RS], acc);
           vacc[k] = acc;
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       // V = half 0 + half 1 (V[16 fb + 4 lk + q][16 n + lr])
@@ -257,28 +258,40 @@ __global__ void __launch_bounds__(NT, 1) k_fused_big(FusedArgs a) {
     }
 
     // ---- pass 2: L_acc[chunk c rows] += X_c V; tile t = w + 8 k of the
-    // chunk's 8 NR output tiles is (row tile t / NR, rank tile t % NR).
+    // chunk's 8 NR output tiles is (row tile t / NR, rank tile t % NR).  The
+    // chunk loop runs at run time; the switch picks the chunk's accumulators
+    // (register arrays need compile-time indices).
+    auto lupd = [&](f4 (&acc)[NR]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int t = w + NW * k;
+        const int m = t / NR, n = t % NR;
+        const float* xr = Xs + (16 * m + lr) * XLD + lk;
+        const float* vb = Vf + lk * RS + 16 * n + lr;
+        f4 ac = acc[k];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) ac = mfma16(xr[4 * ks], vb[4 * ks * RS], ac);
+        acc[k] = ac;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
     load_chunk<T, LAYOUT>(X, v, j0, 0, lane, w, pf, pf_ok);
-#pragma unroll
-    for (int c = 0; c < NCHM; ++c) {
-      if (c < NCH) {
-        __syncthreads();
-        if (MODE == 2 && want_norm)
-          stash_chunk<T, LAYOUT, true>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
-        else stash_chunk<T, LAYOUT, false>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
-        __syncthreads();
-        if (c + 1 < NCH) load_chunk<T, LAYOUT>(X, v, j0, c + 1, lane, w, pf, pf_ok);
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          const int t = w + NW * k;
-          const int m = t / NR, n = t % NR;
-          const float* xr = Xs + (16 * m + lr) * XLD + lk;
-          const float* vb = Vf + lk * RS + 16 * n + lr;
-          f4 acc = lacc[c][k];
-#pragma unroll
-          for (int ks = 0; ks < 16; ++ks) acc = mfma16(xr[4 * ks], vb[4 * ks * RS], acc);
-          lacc[c][k] = acc;
-        }
+    for (int c = 0; c < NCH; ++c) {
+      __syncthreads();
+      if (MODE == 2 && want_norm)
+        stash_chunk<T, LAYOUT, true>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
+      else stash_chunk<T, LAYOUT, false>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
+      __syncthreads();
+      if (c + 1 < NCH) load_chunk<T, LAYOUT>(X, v, j0, c + 1, lane, w, pf, pf_ok);
+      switch (c) {
+        case 0: lupd(lacc[0]); break;
+        case 1: lupd(lacc[1]); break;
+        case 2: lupd(lacc[2]); break;
+        case 3: lupd(lacc[3]); break;
+        case 4: lupd(lacc[4]); break;
+        case 5: lupd(lacc[5]); break;
+        case 6: lupd(lacc[6]); break;
+        default: lupd(lacc[7]); break;
       }
     }
     __syncthreads();
