@@ -98,7 +98,7 @@ struct DevStatus {
 
 // Workspace of one mode solve on view v with rank R.
 struct ModeWs {
-  double *L, *Lnext, *Lacc, *CL, *Cq, *GV, *Q1;
+  double *L, *Lnext, *Lacc, *CL, *Wq, *GV, *Q1;
   void *Lq, *Lr;               // compute type
   void *parts;                 // lacc/Y partials (compute type)
   double *gparts, *sparts;     // Gram partials, scalar partials
@@ -116,7 +116,7 @@ void carve_mode(Arena& ar, int xdt, const View& v, int R, ModeWs& w) {
   w.Lacc = (double*)ar.take(IR * 8);
   w.Q1 = (double*)ar.take(IR * 8);
   w.CL = (double*)ar.take(64 * 64 * 8);
-  w.Cq = (double*)ar.take(64 * 64 * 8);
+  w.Wq = (double*)ar.take(64 * 64 * 8);
   w.GV = (double*)ar.take(64 * 64 * 8);
   w.Lq = ar.take(IR * cs);
   w.Lr = ar.take(IR * cs);
@@ -236,12 +236,12 @@ void init_finish_enqueue(const View& v, int R, int xdt, int resid_mode, ModeWs& 
   StepArgs a{};
   a.m = v.I; a.r = R; a.ops = STEP_QR | STEP_PREP;
   a.Qin = w.Lacc; a.Q1 = w.Q1; a.Qout = w.L;
-  a.Lq = w.Lq; a.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; a.Cq = w.Cq;
+  a.Lq = w.Lq; a.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; a.Wq = w.Wq;
   a.status = &w.st->status; a.prep_status = &w.st->prep_status;
   launch_mode_step(a, cdtype(xdt), s);
 }
 
-// One sweep of Algorithm 3.3 from w.L, whose L~ (w.Lq), Gram factor (w.Cq)
+// One sweep of Algorithm 3.3 from w.L, whose L~ (w.Lq), inverse Gram factor (w.Wq)
 // and compute-type copy (w.Lr, explicit residual) are already prepared:
 // R-update (never stored when fused), L-update into w.Lnext, residual into
 // st->res2, and the speculative preparation of the sweep from w.Lnext.
@@ -293,7 +293,7 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
     a.rsum = &w.st->rsum;
   }
   a.res2 = &w.st->res2;
-  a.Lq = w.Lq; a.Lr = expl ? w.Lr : nullptr; a.Cq = w.Cq;
+  a.Lq = w.Lq; a.Lr = expl ? w.Lr : nullptr; a.Wq = w.Wq;
   a.status = &w.st->status; a.prep_status = &w.st->prep_status;
   launch_mode_step(a, cdt, s);
 }
@@ -720,7 +720,7 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
     StepArgs p{};
     p.m = v.I; p.r = R; p.ops = STEP_PREP;
     p.Qin = w.L;
-    p.Lq = w.Lq; p.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; p.Cq = w.Cq;
+    p.Lq = w.Lq; p.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; p.Wq = w.Wq;
     p.status = &w.st->status; p.prep_status = &w.st->prep_status;
     launch_mode_step(p, cdtype(a_dtype), s);
   }

@@ -116,14 +116,15 @@ enum { STEP_SOLVE = 1, STEP_QR = 2, STEP_PREP = 4, STEP_PREP_SPECULATIVE = 8 };
 struct StepArgs {
   int64_t m; int r; int ops;
   // SOLVE: Lnext = Lacc GV^{-1}; res2[0] = rsum ? *rsum : norm2 - tr(Gq^-1 GV),
-  // res2[1] = tr(Gq^-1 GV) with Gq = Cq Cq^T (Cq as left by the last PREP)
+  // res2[1] = tr(Gq^-1 GV) with Gq^-1 = Wq^T Wq (Wq as left by the last PREP)
   const double* Lacc; const double* GV; double* Lnext;
   double norm2; const double* rsum; double* res2;
   // QR: Qout = Q of the reduced QR of Qin (Q1: m x r scratch)
   const double* Qin; double* Q1; double* Qout;
   // PREP from Lnext (SOLVE) or Qout (QR): Lq = L (L^T L)^{-1} in the compute
-  // type, Cq = chol(Lq^T Lq), Lr = L in the compute type (if non-null)
-  void* Lq; void* Lr; double* Cq;
+  // type, Wq = chol(Lq^T Lq)^{-1} (r x r lower, row-major), Lr = L in the
+  // compute type (if non-null)
+  void* Lq; void* Lr; double* Wq;
   int* status;        // failures of SOLVE / QR / non-speculative PREP
   int* prep_status;   // failures of a speculative PREP
 };
