@@ -77,8 +77,11 @@ __host__ __device__ inline Lds lds_layout(int I, int NR, int mode) {
 // compiler issues them back to back without branches (duplicates of a
 // clamped row hit the caches).
 //  LAYOUT 0 (Q > 1): slot k is row ii = 8k + w of fibre j0 + lane
-//          (coalesced along q); lanes past the last fibre read fibre j0 and
-//          are zeroed in the stash.
+//          (coalesced along q); lanes past the last fibre read the last
+//          fibre and are zeroed in the stash.
+// Tiles past the end are fetched the same way (clamped), so that every
+// prefetch is unconditional and the wait for one buffer never covers the
+// loads of the other.
 //  LAYOUT 1 (Q == 1): slot k = NC f + c is rows lane + 64c of fibre
 //          j0 + w + 8f (NC = IC/8 chunks of 64 rows per fibre, 8 fibres).
 template <typename T, int LAYOUT, int IC>
@@ -89,7 +92,7 @@ __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v,
   if (LAYOUT == 0) {
     const int64_t j = j0 + lane;
     ok = j < J;
-    const T* b = X + v.fibre_base(ok ? j : j0);
+    const T* b = X + v.fibre_base(ok ? j : J - 1);
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
       const int ii = min(NW * k + w, I - 1);
@@ -113,12 +116,16 @@ template <typename T, int LAYOUT, int IC, bool NORM>
 __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w, const T* pf,
                                       bool ok, int xrows, float* Xs, double& nsum) {
   const int I = (int)v.I;
+  // (the masking of lanes past the last fibre is a bitwise and, not a
+  // select: a branch here makes the compiler wait for every load in flight,
+  // the next tile's included)
   if (LAYOUT == 0) {
+    const uint32_t keep = ok ? 0xffffffffu : 0u;
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
       const int ii = NW * k + w;
       const int row = ii < I ? ii : xrows;
-      const float x = ok ? to_f<T>(pf[k]) : 0.0f;
+      const float x = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, to_f<T>(pf[k])) & keep);
       Xs[row * XLD + lane] = x;
       if (NORM && ii < I) nsum += (double)x * (double)x;
     }
@@ -128,10 +135,10 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
       const int f = k / NC, c = k % NC;
-      const bool fok = j0 + w + NW * f < J;
+      const uint32_t keep = (j0 + w + NW * f < J) ? 0xffffffffu : 0u;
       const int ii = lane + 64 * c;
       const int row = ii < I ? ii : xrows;
-      const float x = fok ? to_f<T>(pf[k]) : 0.0f;
+      const float x = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, to_f<T>(pf[k])) & keep);
       Xs[row * XLD + w + NW * f] = x;
       if (NORM && ii < I) nsum += (double)x * (double)x;
     }
@@ -204,8 +211,8 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   T pf0[IC], pf1[IC];
   bool ok0 = false, ok1 = false;
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf0, ok0);
-  if (tile + nwg < ntiles) prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf1, ok1);
+  prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf0, ok0);
+  prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf1, ok1);
 
   auto body = [&](const int64_t tile, T (&pf)[IC], bool& pf_ok) __attribute__((always_inline)) {
     const int64_t j0 = tile * TJ;
@@ -214,8 +221,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     else stash<T, LAYOUT, IC, false>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
     __syncthreads();
     // this buffer now fetches the tile after the one the other buffer holds
-    if (tile + 2 * nwg < ntiles)
-      prefetch<T, LAYOUT, IC>(X, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
+    prefetch<T, LAYOUT, IC>(X, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
 
     if (MODE != 2) {
       // R-update: tile (fibre block f, rank tile n): A = X^T (16 fibres x
@@ -373,10 +379,11 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   
   };
 
-  for (; tile < ntiles; tile += 2 * nwg) {
+  for (; tile + nwg < ntiles; tile += 2 * nwg) {
     body(tile, pf0, ok0);
-    if (tile + nwg < ntiles) body(tile + nwg, pf1, ok1);
+    body(tile + nwg, pf1, ok1);
   }
+  if (tile < ntiles) body(tile, pf0, ok0);
 
   // ---- per-workgroup outputs
   const int wg = blockIdx.x;
