@@ -72,7 +72,7 @@ __host__ __device__ inline Lds lds_layout(int I, int NR, int mode) {
 }
 
 // Prefetch of one tile into registers: a fixed number of unconditional
-// loads per lane (IC = 8, 16 or 32 row slots per wave, from the mode size
+// loads per lane (IC = 8, 16, 26 or 32 row slots per wave, from the mode size
 // class) whose row / fibre indices are clamped into the tensor, so the
 // compiler issues them back to back without branches (duplicates of a
 // clamped row hit the caches).
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   constexpr int LRS = RP + 1;                // Lr row stride
   constexpr int NG = NR * (NR + 1) / 2;      // Gram output tiles
   constexpr int U1 = (4 * NR + NW - 1) / NW; // R-update tiles per wave (max)
-  constexpr int RT = IC == 32 ? 2 : 1;       // L-update row tiles per wave (MT <= 8 RT)
+  constexpr int RT = IC > 16 ? 2 : 1;        // L-update row tiles per wave (MT <= 8 RT)
   constexpr int U2 = RT * NR;                // L-update tiles per wave
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
@@ -235,29 +235,41 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
           const int fb = t / NR, n = t % NR;
           const float* xa = Xs + lk * XLD + 16 * fb + lr;
           const float* lb = Lq + lk * RS + 16 * n + lr;
-          f4 vacc = f4{0, 0, 0, 0};
-          float ca[4], cb[4];
+          // Two register sets of stage operands in ping-pong: the reads of
+          // the next stage are in flight while the current one multiplies,
+          // and no register copy forces a wait for them.  Four independent
+          // accumulation chains (one per 4-row K step of a stage) are added
+          // in a fixed order at the end.
+          f4 vq[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            ca[q] = xa[4 * q * XLD];
-            cb[q] = lb[4 * q * RS];
-          }
-          for (int st = 0; st < MT; ++st) {
-            const int nx = 16 * (st + 1 < MT ? st + 1 : st);
-            float na[4], nb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              na[q] = xa[(nx + 4 * q) * XLD];
-              nb[q] = lb[(nx + 4 * q) * RS];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) vacc = mfma16(ca[q], cb[q], vacc);
+          for (int q = 0; q < 4; ++q) vq[q] = f4{0, 0, 0, 0};
+          float a0[4], b0[4], a1[4], b1[4];
+          auto ld = [&](float* ca, float* cb, int st) __attribute__((always_inline)) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              ca[q] = na[q];
-              cb[q] = nb[q];
+              ca[q] = xa[(16 * st + 4 * q) * XLD];
+              cb[q] = lb[(16 * st + 4 * q) * RS];
             }
+          };
+          auto mm = [&](const float* ca, const float* cb) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vq[q] = mfma16(ca[q], cb[q], vq[q]);
+          };
+          ld(a0, b0, 0);
+          int st = 0;
+          // (scheduling barriers keep the reads ahead of the products)
+          for (; st + 1 < MT; st += 2) {
+            ld(a1, b1, st + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            mm(a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            ld(a0, b0, st + 2 < MT ? st + 2 : MT - 1);
+            __builtin_amdgcn_sched_barrier(0);
+            mm(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
           }
+          if (st < MT) mm(a0, b0);
+          const f4 vacc = (vq[0] + vq[1]) + (vq[2] + vq[3]);
           // V[16 fb + 4 lk + q][16 n + lr] = vacc[q]
           if (MODE == 3) {
 #pragma unroll
@@ -442,18 +454,21 @@ void launch_ic(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
     hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL((k_fused<T, NR, MODE, 0, IC>), dim3(nwg), dim3(NT), bytes, s, a);
-  } else {
+  } else if constexpr (IC % 8 == 0) {      // Q == 1 slots are 64-row chunks
     hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 1, IC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL((k_fused<T, NR, MODE, 1, IC>), dim3(nwg), dim3(NT), bytes, s, a);
   }
 }
 
-// Row-slot class: 8, 16 or 32 slots per wave (I <= 64, 128, 256).
+// Row-slot class: 8, 16, 26 or 32 slots per wave (I <= 64, 128, 208, 256;
+// the 26-slot class keeps two tiles of loads under the 63 outstanding loads
+// of a wave, and is taken only for Q > 1, whose slots are single rows).
 template <typename T, int NR, int MODE>
 void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
   if (a.v.I <= 64) launch_ic<T, NR, MODE, 8>(a, nwg, bytes, s);
   else if (a.v.I <= 128) launch_ic<T, NR, MODE, 16>(a, nwg, bytes, s);
+  else if (a.v.I <= 208 && a.v.Q != 1) launch_ic<T, NR, MODE, 26>(a, nwg, bytes, s);
   else launch_ic<T, NR, MODE, 32>(a, nwg, bytes, s);
 }
 

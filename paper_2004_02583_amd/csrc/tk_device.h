@@ -12,8 +12,15 @@ struct View {
   int64_t P, I, Q;
   __host__ __device__ int64_t J() const { return P * Q; }
   __host__ __device__ int64_t fibre_base(int64_t j) const {
-    int64_t p = j / Q;
-    int64_t q = j - p * Q;
+    int64_t p, q;
+    if (((uint64_t)j | (uint64_t)Q) < (1ull << 32)) {   // 32-bit division when it fits
+      const uint32_t pj = (uint32_t)j / (uint32_t)Q;
+      p = pj;
+      q = (uint32_t)j - pj * (uint32_t)Q;
+    } else {
+      p = j / Q;
+      q = j - p * Q;
+    }
     return p * I * Q + q;
   }
 };
