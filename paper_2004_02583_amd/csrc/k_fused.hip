@@ -119,6 +119,9 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
   // (the masking of lanes past the last fibre is a bitwise and, not a
   // select: a branch here makes the compiler wait for every load in flight,
   // the next tile's included)
+  // (the squares go to four partial sums: one FP64 chain would wait out the
+  // FMA latency at every element)
+  double ns[4] = {0.0, 0.0, 0.0, 0.0};
   if (LAYOUT == 0) {
     const uint32_t keep = ok ? 0xffffffffu : 0u;
 #pragma unroll
@@ -127,7 +130,7 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
       const int row = ii < I ? ii : xrows;
       const float x = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, to_f<T>(pf[k])) & keep);
       Xs[row * XLD + lane] = x;
-      if (NORM && ii < I) nsum += (double)x * (double)x;
+      if (NORM && ii < I) ns[k & 3] += (double)x * (double)x;
     }
   } else {
     const int64_t J = v.J();
@@ -140,9 +143,10 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
       const int row = ii < I ? ii : xrows;
       const float x = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, to_f<T>(pf[k])) & keep);
       Xs[row * XLD + w + NW * f] = x;
-      if (NORM && ii < I) nsum += (double)x * (double)x;
+      if (NORM && ii < I) ns[k & 3] += (double)x * (double)x;
     }
   }
+  if (NORM) nsum += (ns[0] + ns[1]) + (ns[2] + ns[3]);
 }
 
 // MODE 0: sweep; 1: sweep + explicit residual; 2: init (sketch, no Gram);

@@ -106,6 +106,9 @@ template <int IC, bool NORM>
 __device__ __forceinline__ void stash(const View& v, int lane, int w, const uint32_t* pf,
                                       bool ok, int XR, uint32_t* Xs32, double& nsum) {
   const int I = (int)v.I;
+  // (the squares go to four partial sums: one FP64 chain would wait out the
+  // FMA latency at every element)
+  double ns[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < IC; ++k) {
     const int ii = NW * k + w;
@@ -114,9 +117,10 @@ __device__ __forceinline__ void stash(const View& v, int lane, int w, const uint
     Xs32[xidx(row, 2 * lane) >> 1] = x;
     if (NORM && ii < I) {
       const float a = bf16_to_f32((bf16_t)(x & 0xffffu)), b = bf16_to_f32((bf16_t)(x >> 16));
-      nsum += (double)a * (double)a + (double)b * (double)b;
+      ns[k & 3] += (double)a * (double)a + (double)b * (double)b;
     }
   }
+  if (NORM) nsum += (ns[0] + ns[1]) + (ns[2] + ns[3]);
 }
 
 // MODE 0: sweep; 2: init (sketch, norm, no Gram); 3: TTM.

@@ -96,6 +96,9 @@ template <typename T, int LAYOUT, bool NORM>
 __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, int lane, int w,
                                             const T* pf, bool ok, float* Xs, double& nsum) {
   const int I = (int)v.I;
+  // (the squares go to four partial sums: one FP64 chain would wait out the
+  // FMA latency at every element)
+  double ns[4] = {0.0, 0.0, 0.0, 0.0};
   if (LAYOUT == 0) {
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
@@ -103,7 +106,7 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
       const bool in = CH * c + r < I;
       const float x = ok ? to_f<T>(pf[k]) : 0.0f;
       Xs[(in ? r : CH) * XLD + lane] = x;
-      if (NORM && in) nsum += (double)x * (double)x;
+      if (NORM && in) ns[k & 3] += (double)x * (double)x;
     }
   } else {
     const int64_t J = v.J();
@@ -115,9 +118,10 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
       const bool in = CH * c + r < I;
       const float x = fok ? to_f<T>(pf[k]) : 0.0f;
       Xs[(in ? r : CH) * XLD + w + NW * f] = x;
-      if (NORM && in) nsum += (double)x * (double)x;
+      if (NORM && in) ns[k & 3] += (double)x * (double)x;
     }
   }
+  if (NORM) nsum += (ns[0] + ns[1]) + (ns[2] + ns[3]);
 }
 
 // MODE 0: sweep; 2: init (sketch, norm, no Gram); 3: TTM.
