@@ -178,9 +178,25 @@ void qr_enqueue(const double* L, int64_t m, int r, double* Q, double* Q1, int* s
   launch_mode_step(a, TK_F64, s);
 }
 
+// The status block is read through a small pinned host buffer of the calling
+// thread (allocated on first use, kept for the life of the thread: a copy
+// into pageable memory goes through a runtime staging buffer and costs a
+// longer round trip on every sweep).
+DevStatus* pinned_status() {
+  thread_local DevStatus* p = nullptr;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (hipHostMalloc((void**)&p, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) p = nullptr;
+  }
+  return p;
+}
+
 int read_status(const DevStatus* d, DevStatus* h, hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(h, d, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  DevStatus* ph = pinned_status();
+  HIPCHK(hipMemcpyAsync(ph ? ph : h, d, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (ph) *h = *ph;
   return TK_OK;
 }
 
