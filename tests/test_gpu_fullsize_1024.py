@@ -1,0 +1,130 @@
+"""Checks at the full size of the large-mode workload (1024^3 FP32 tensor, core 64^3 with
+0.9^(i+j+k) decay, 1e-3 relative noise, t-HOSVD-ALS to ranks 48^3, eta = 1e-4): sampled TTM
+fibres against the oracle, and properties that hold at any size, among them the error bounds
+from the trailing eigenvalues of the FP64 mode Grams (plain PyTorch on the device, not this
+library)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tucker_oracle as o
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+I, C, R = 1024, 64, 48
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big(gpu_lib):
+    flush("generating the 1024^3 FP32 workload")
+    A, _, Us = synth.tucker_lowrank_torch(2, (I,) * 3, (C,) * 3, 1e-3,
+                                          decay=synth.decay_geom((C,) * 3, 0.9),
+                                          device="cuda", out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    yield dict(A=A, factors=Us)
+    del A
+    torch.cuda.empty_cache()
+
+
+def _relerr(tk, A, G, Us):
+    """||A - A_hat|| / ||A|| in FP64 over slabs of mode 1, and ||A||."""
+    Ah = tk.tucker_reconstruct(G, Us)
+    num = den = 0.0
+    for s in range(0, I, 64):
+        a = A[s:s + 64].double()
+        num += float(((a - Ah[s:s + 64].double()) ** 2).sum())
+        den += float((a * a).sum())
+    del Ah
+    return (num / den) ** 0.5, den ** 0.5
+
+
+def _trailing_energies(A):
+    """gamma_n = sum of the eigenvalues of the FP64 mode Gram A_(n) A_(n)^T past the R
+    largest (torch.linalg.eigh), and ||A||^2."""
+    A64 = A.double()
+    nA2 = float((A64 * A64).sum())
+    gam = []
+    for n in range(3):
+        X = A64.movedim(n, 0).reshape(I, -1)
+        w = torch.linalg.eigvalsh(X @ X.T)
+        gam.append(max(nA2 - float(w[-R:].sum()), 0.0))
+        del X
+    del A64
+    return gam, nA2
+
+
+def test_1024_thosvd_properties(gpu_lib, big):
+    """FP32 t-HOSVD-ALS at full size: orthonormal factors, Pythagoras with the core, and an
+    error between the best single-mode truncation error and the Thm 4 bound."""
+    tk = gpu_lib
+    A = big["A"]
+    flush("1024^3 t-HOSVD-ALS FP32")
+    G, Us, info = tk.als_thosvd(A, (R,) * 3, tol=1e-4)
+    assert info["status"] == "TK_OK"
+    assert tuple(G.shape) == (R, R, R)
+    for U in Us:
+        Uh = U.double().cpu().numpy()
+        np.testing.assert_allclose(Uh.T @ Uh, np.eye(R), atol=1e-5)
+    e, nA = _relerr(tk, A, G, Us)
+    assert abs(nA - info["norm_a"]) <= 1e-9 * nA
+    g2 = float((G.double() ** 2).sum())
+    # ||A||^2 - ||G||^2 = ||A - A_hat||^2 up to FP32 rounding of G (~1e-7 ||A||^2 against
+    # ~8e-5 ||A||^2 here)
+    assert abs(nA ** 2 - g2 - (e * nA) ** 2) <= 0.01 * (e * nA) ** 2
+    flush("1024^3 Gram eigenvalues")
+    gam, nA2 = _trailing_energies(A)
+    err = e * nA
+    # below: no projection onto R_n-dimensional mode-n subspaces beats the best one
+    # (Eckart-Young on each unfolding); above: the t-HOSVD-ALS bound of Thm 4 with its cross
+    # term, sqrt(sum_n (eta ||A|| + sqrt(gamma_n))^2)
+    assert max(gam) ** 0.5 <= err * (1 + 1e-6), (gam, err)
+    upper = sum((1e-4 * nA + g ** 0.5) ** 2 for g in gam) ** 0.5
+    assert err <= upper, (err, upper)
+
+
+def test_1024_thosvd_bf16_storage(gpu_lib, big):
+    """BF16 storage at full size: error against the FP32 tensor within the BF16 gate of the
+    FP32 result, and in practice equal to it to a few parts in a thousand."""
+    tk = gpu_lib
+    A = big["A"]
+    flush("1024^3 t-HOSVD-ALS FP32 (reference for BF16)")
+    G, Us, info = tk.als_thosvd(A, (R,) * 3, tol=1e-4)
+    e32, _ = _relerr(tk, A, G, Us)
+    del G, Us
+    Ab = A.to(torch.bfloat16)
+    flush("1024^3 t-HOSVD-ALS BF16 storage")
+    Gb, Ub, infob = tk.als_thosvd(Ab, (R,) * 3, tol=1e-4)
+    del Ab
+    assert infob["status"] in ("TK_OK", "TK_NOT_CONVERGED")
+    eb, _ = _relerr(tk, A, Gb, Ub)
+    assert eb <= e32 + 1e-2, (eb, e32)
+    assert eb <= 1.005 * e32, (eb, e32)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_1024_ttm_sampled(gpu_lib, big, mode):
+    """Y = A x_n U^T at 1024^3 through the large-mode kernels (mode 1: P = 1; mode 3:
+    Q = 1): 32 sampled fibres of Y against the oracle's TTM of the same fibres of A, within
+    the FP32 accumulation bound."""
+    tk = gpu_lib
+    A = big["A"]
+    rng = np.random.default_rng(91 + mode)
+    U = synth.orthonormal(rng, I, R).astype(np.float32)
+    flush(f"1024^3 ttm mode={mode}")
+    Y = tk.ttm(A, torch.from_numpy(U).cuda(), mode, transpose=True)
+    assert tuple(Y.shape) == tuple(R if k == mode else I for k in range(3))
+    Uh = U.astype(np.float64)
+    for _ in range(32):
+        idx = [int(rng.integers(0, I)) for _ in range(2)]
+        sl = list(idx)
+        sl.insert(mode, slice(None))
+        a = A[tuple(sl)].double().cpu().numpy()
+        want = o.ttm(a[:, None], Uh.T, 0)[:, 0]
+        got = Y[tuple(sl)].double().cpu().numpy()
+        bound = I * 2.0 ** -24 * (np.abs(Uh).T @ np.abs(a))
+        assert np.all(np.abs(got - want) <= 4 * bound + 1e-30), (idx, np.abs(got - want).max())
