@@ -53,6 +53,8 @@ TTM_CASES = [
     ((33, 256, 17), 1, 48, False),  # largest mode and output width of the MFMA TTM
     ((40, 520, 9), 1, 48, True),    # large-mode TTM (chunked rows)
     ((33, 700), 1, 20, False),      # large-mode TTM, Q == 1
+    ((9, 70, 40), 1, 19, True),     # TTM width 16 < J <= 20
+    ((33, 60), 1, 17, False),       # TTM width 16 < J <= 20, Q == 1
 ]
 
 
@@ -110,7 +112,9 @@ def test_contract_allbut_parity(gpu_lib, dt):
 # --------------------------------------------------- single steps of ALS
 
 STEP_CASES = [((20, 30, 40), 0, 5), ((20, 30, 40), 1, 7), ((20, 30, 40), 2, 6),
-              ((100, 9, 70), 0, 20), ((12, 11, 10, 9), 2, 4)]
+              ((100, 9, 70), 0, 20), ((12, 11, 10, 9), 2, 4),
+              ((30, 64, 50), 1, 18),      # second rank tile mostly padding, I = 64, tiles straddle p
+              ((40, 150, 30), 1, 19)]     # second rank tile mostly padding, ragged row tiles
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -297,6 +301,9 @@ KERNEL_CASES = [
     ((7, 600, 33), 1, 40),      # I = 600: ragged last chunk, tiles straddle p
     ((50, 1024), 1, 48),        # I = 1024, Q == 1, R = 48, one ragged tile
     ((1100, 8, 9), 0, 5),       # I > 1024: generic two-pass kernels
+    ((20, 200, 50), 1, 17),     # 16 < R <= 20 (second rank tile mostly padding), Q < 64
+    ((30, 40, 200), 2, 19),     # 16 < R <= 20, Q == 1
+    ((64, 37, 70), 1, 18),      # 16 < R <= 20, ragged small mode
 ]
 
 
