@@ -168,7 +168,6 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int MT = (I + 15) / 16;              // 16-row tiles of the mode
-  const int KS = (I + 3) / 4;                // 4-row K steps of the R-update
   const int xrows = 16 * MT;
   const Lds L = lds_layout(I, NR, MODE);
   float* Xs = smem + L.xs;
@@ -455,11 +454,11 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 template <typename T, int NR, int MODE, int IC>
 void launch_ic(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
   if (a.v.Q != 1) {
-    hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC>,
+    (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL((k_fused<T, NR, MODE, 0, IC>), dim3(nwg), dim3(NT), bytes, s, a);
   } else if constexpr (IC % 8 == 0) {      // Q == 1 slots are 64-row chunks
-    hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 1, IC>,
+    (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 1, IC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL((k_fused<T, NR, MODE, 1, IC>), dim3(nwg), dim3(NT), bytes, s, a);
   }
