@@ -91,7 +91,7 @@ typedef struct {
   int32_t resid_mode;      /* tk_resid_mode (default TK_RESID_TRACE)          */
   uint64_t seed;           /* seed of the initial sketch S (Section 5)        */
   const int32_t* order;    /* host; st-HOSVD processing order, a permutation
-                              of 0..N-1 (Algorithm 3.5 line 1); NULL = 0..N-1 */
+                              of 0..N-1 (Algorithm 3.5); NULL = 0..N-1      */
 } tk_als_opts;
 
 /* Per-call report. */
@@ -223,8 +223,8 @@ TK_API int qr_f64(const void* L, int64_t m, int32_t r, void* Q, void* Rhat,
            void* ws, size_t ws_bytes, void* stream);
 
 /* als_sweep_kernel: the tensor-streaming part of one ALS sweep alone
- * (Algorithm 3.3 lines 4 and 6 without the small solves), for timing and
- * step checking.  With Lq = L_k (L_k^T L_k)^{-1} (FP32, I_mode x R,
+ * (the R- and L-updates of Algorithm 3.3 without their small solves), for
+ * timing and step checking.  With Lq = L_k (L_k^T L_k)^{-1} (FP32, I_mode x R,
  * device): V = A_(mode)^T Lq (never stored), GV = V^T V (FP64 R x R) and
  * Lacc = A_(mode) V (FP64 I_mode x R).  When `reduce` is 0 only the
  * streaming kernel runs and leaves per-workgroup partials in ws (Lacc and

@@ -371,7 +371,7 @@ def sthosvd_als(A: np.ndarray, ranks, order=None, tol: float = 1e-4,
 
 def leading_left_singular_vectors(M: np.ndarray, R: int,
                                   method: str = "auto") -> np.ndarray:
-    """Leading R left singular vectors of M (Algorithm 3.1, line 2).  The EIG
+    """Leading R left singular vectors of M (the SVD step of Algorithm 3.1).  The EIG
     route uses eigenvectors of the Gram M M^T (the remark after Alg. 3.1)."""
     M = np.asarray(M, dtype=np.float64)
     if method == "auto":

@@ -512,7 +512,7 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
     }
   }
   if (which == 0) {
-    // G = A x_1 U_1^T ... x_N U_N^T (Algorithm 3.4 last line)
+    // G = A x_1 U_1^T ... x_N U_N^T (the core of Algorithm 3.4)
     for (int t = 0; t < N; ++t) {
       void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
       rc = ttm_enqueue(B, bdt, N, cur, t, U[t], ranks[t], 1, dst, s);
