@@ -35,10 +35,18 @@ in the design notes of the repository):
   means R_n exceeds the numerical rank (Remark 3): ``RankDeficient`` is
   raised, no regularisation.
 * QR sign convention: diag(R_hat) >= 0.
+* Singular vectors for t-HOSVD-ALS (the optional replacement of the factor
+  step of Algorithm 3.4, Section 3): columns in descending order of the
+  singular values of Q_hat^T A_(n); each column of the small left factor U is
+  signed so that its entry of largest magnitude is positive.
+* st-HOSVD processing order: the automatic order is the permutation of least
+  cost under eq. 2.2 (Prop. 1) over all N! orders, the first in lexicographic
+  order among equal costs.
 """
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import numpy as np
 import scipy.linalg as sla
 
@@ -312,16 +320,33 @@ def _mode_factor(Bn: np.ndarray, R: int, seed: int, mode: int, tol: float,
                                     res.residuals[-1])
 
 
+def singular_vectors_from_basis(An: np.ndarray, Q: np.ndarray):
+    """Singular vectors from an orthonormal basis Q of the dominant subspace
+    (Section 3, after Algorithm 3.4): the SVD U S V^T of C = Q^T A_(n), then
+    Q U.  Singular values come out in descending order; each column of U is
+    signed so that its entry of largest magnitude is positive (reading above).
+    Returns (Q U, singular values of C)."""
+    C = Q.T @ An
+    U, s, _ = np.linalg.svd(C, full_matrices=False)
+    cols = np.arange(U.shape[1])
+    U = U * np.sign(U[np.argmax(np.abs(U), axis=0), cols])
+    return Q @ U, s
+
+
 def thosvd_als(A: np.ndarray, ranks, tol: float = 1e-4, max_iters: int = 50,
-               seed: int = 0) -> TuckerResult:
+               seed: int = 0, singular_vectors: bool = False) -> TuckerResult:
     """Algorithm 3.4 (t-HOSVD-ALS): per mode, ALS on A_(n), U^(n) = Q of the
-    reduced QR of L; then G = A x_1 U^(1)T ... x_N U^(N)T."""
+    reduced QR of L; then G = A x_1 U^(1)T ... x_N U^(N)T.  With
+    ``singular_vectors`` the factor step is replaced by the singular vectors
+    of A_(n) within that basis (``singular_vectors_from_basis``)."""
     A = np.asarray(A, dtype=np.float64)
     nA = frob(A)
     Us, infos = [], []
     for n in range(A.ndim):
         U, _, _, info = _mode_factor(unfold(A, n), ranks[n], seed, n, tol,
                                      max_iters, nA)
+        if singular_vectors:
+            U, _ = singular_vectors_from_basis(unfold(A, n), U)
         Us.append(U)
         infos.append(info)
     G = core_from_factors(A, Us)
@@ -362,6 +387,36 @@ def sthosvd_als(A: np.ndarray, ranks, order=None, tol: float = 1e-4,
         Us[n] = U
         infos[n] = info
     return TuckerResult(B, Us, infos, nA)
+
+
+def st_order_cost(dims, ranks, order) -> int:
+    """Cost model of eq. 2.2 (proof of Prop. 1) for processing the modes of
+    st-HOSVD in ``order`` = (i_1, ..., i_N): the sum over n of
+    R_{i_1} ... R_{i_n} times I_{i_n} ... I_{i_N}, in exact integers."""
+    order = list(order)
+    total = 0
+    for n in range(len(order)):
+        r = 1
+        for k in order[:n + 1]:
+            r *= int(ranks[k])
+        i = 1
+        for k in order[n:]:
+            i *= int(dims[k])
+        total += r * i
+    return total
+
+
+def st_order_auto(dims, ranks) -> list:
+    """The st-HOSVD processing order of least eq. 2.2 cost over all N!
+    permutations, the first in lexicographic order among equal costs (reading
+    above).  With equal dimensions this is the order of ascending ranks
+    (Prop. 1)."""
+    best, best_cost = None, None
+    for perm in itertools.permutations(range(len(dims))):
+        c = st_order_cost(dims, ranks, perm)
+        if best_cost is None or c < best_cost:
+            best, best_cost = list(perm), c
+    return best
 
 
 # --------------------------------------------------------------------------

@@ -333,6 +333,99 @@ def test_full_rank_mode_is_identity():
     assert res.info[0].iters == 0
 
 
+def test_singular_vectors_exact_low_rank():
+    """Singular vectors from the ALS basis (Section 3, after Algorithm 3.4) on an exactly
+    low-rank tensor: each U^(n) matches the leading left singular vectors of A_(n) from
+    numpy's SVD of the unfolding (up to sign), the core is all-orthogonal with
+    G_(n) G_(n)^T = diag(sigma_1^2, ..., sigma_R^2) of A_(n) (the HOSVD property), and the
+    error equals that of the plain ALS basis (same subspaces)."""
+    rng = np.random.default_rng(31)
+    dims, ranks = (12, 10, 9), (5, 4, 3)
+    A = synth.tucker_lowrank(rng, dims, ranks, 0.0,
+                             decay=synth.decay_geom(ranks, 0.6))[0]
+    sv = o.thosvd_als(A, ranks, tol=1e-12, singular_vectors=True)
+    plain = o.thosvd_als(A, ranks, tol=1e-12)
+    nA = o.frob(A)
+    for n in range(3):
+        X, s, _ = np.linalg.svd(o.unfold(A, n), full_matrices=False)
+        R = ranks[n]
+        d = np.abs(np.sum(X[:, :R] * sv.U[n], axis=0))
+        np.testing.assert_allclose(d, np.ones(R), atol=1e-9)
+        np.testing.assert_allclose(sv.U[n].T @ sv.U[n], np.eye(R), atol=1e-13)
+        Gn = o.unfold(sv.G, n)
+        np.testing.assert_allclose(Gn @ Gn.T, np.diag(s[:R] ** 2), atol=1e-10 * nA ** 2)
+        # same subspace as the QR basis
+        assert np.max(o.principal_angles(sv.U[n], plain.U[n])) < 1e-7
+    assert abs(o.relerr(A, sv.G, sv.U) - o.relerr(A, plain.G, plain.U)) < 1e-12
+
+
+def test_singular_vectors_from_basis_order_and_sign():
+    """Columns follow descending singular values of Q^T A_(n) (checked against the
+    eigenvalues of the Gram) and the small factor W = Q^T U^(n) has its largest-magnitude
+    entry positive in every column."""
+    rng = np.random.default_rng(32)
+    An = rng.standard_normal((15, 40))
+    Q = synth.orthonormal(rng, 15, 6)
+    U, s = o.singular_vectors_from_basis(An, Q)
+    ev = np.linalg.eigvalsh(Q.T @ An @ An.T @ Q)[::-1]
+    np.testing.assert_allclose(s ** 2, ev, rtol=1e-12)
+    assert np.all(np.diff(s) <= 0)
+    W = Q.T @ U
+    np.testing.assert_allclose(W.T @ W, np.eye(6), atol=1e-13)
+    for c in range(6):
+        assert W[np.argmax(np.abs(W[:, c])), c] > 0
+    # U^T A_(n) A_(n)^T U is diagonal: the columns are the singular directions
+    M = U.T @ An @ An.T @ U
+    np.testing.assert_allclose(M, np.diag(s ** 2), atol=1e-10 * s[0] ** 2)
+
+
+def _st_cost_by_shapes(dims, ranks, order):
+    """Work of st-HOSVD (Algorithm 3.2) counted on the shrinking tensor: mode n costs
+    R_n times the number of entries of the tensor it is applied to, which then has its
+    mode n cut to R_n."""
+    shape = list(dims)
+    total = 0
+    for n in order:
+        total += ranks[n] * int(np.prod(shape, dtype=object))
+        shape[n] = ranks[n]
+    return total
+
+
+def test_st_order_cost_matches_shrinking_shapes():
+    import itertools
+    rng = np.random.default_rng(33)
+    for N in (2, 3, 4, 5):
+        for _ in range(5):
+            dims = [int(x) for x in rng.integers(2, 40, N)]
+            ranks = [int(rng.integers(1, d + 1)) for d in dims]
+            for perm in itertools.permutations(range(N)):
+                assert o.st_order_cost(dims, ranks, perm) == _st_cost_by_shapes(dims, ranks, perm)
+    # worked by hand: dims (10, 20, 30), ranks (5, 2, 3), natural order:
+    # 5*6000 + 10*600 + 30*30
+    assert o.st_order_cost((10, 20, 30), (5, 2, 3), (0, 1, 2)) == 36900
+
+
+def test_st_order_auto_prop1_and_ties():
+    """Prop. 1: with equal dimensions the order of ascending ranks is cheapest; equal costs
+    resolve to the first order in lexicographic order; the result is a true minimiser."""
+    import itertools
+    rng = np.random.default_rng(34)
+    for N in (3, 4, 5):
+        for _ in range(4):
+            ranks = [int(x) for x in rng.choice(np.arange(1, 30), N, replace=False)]
+            assert o.st_order_auto([40] * N, ranks) == list(np.argsort(ranks))
+    assert o.st_order_auto([16] * 4, [3] * 4) == [0, 1, 2, 3]
+    assert o.st_order_auto([16, 16, 16], [5, 2, 2]) == [1, 2, 0]
+    for _ in range(10):
+        dims = [int(x) for x in rng.integers(2, 60, 4)]
+        ranks = [int(rng.integers(1, d + 1)) for d in dims]
+        best = o.st_order_auto(dims, ranks)
+        costs = {p: _st_cost_by_shapes(dims, ranks, p) for p in itertools.permutations(range(4))}
+        m = min(costs.values())
+        assert costs[tuple(best)] == m
+        assert tuple(best) == min(p for p, c in costs.items() if c == m)
+
+
 # ---------------------------------------------------------- P8: gradients
 
 def _fd(f, x, d, h=1e-3):
