@@ -92,6 +92,10 @@ typedef struct {
   uint64_t seed;           /* seed of the initial sketch S (Section 5)        */
   const int32_t* order;    /* host; st-HOSVD processing order, a permutation
                               of 0..N-1 (Algorithm 3.5); NULL = 0..N-1      */
+  int32_t singular_vectors; /* als_thosvd only: nonzero replaces each factor
+                              by the singular vectors of A_(n) within its
+                              span (Section 3, after Algorithm 3.4); 0 keeps
+                              the QR basis (default)                        */
 } tk_als_opts;
 
 /* Per-call report. */
@@ -135,7 +139,16 @@ TK_API int als_sthosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t*
 /* als_thosvd -- Algorithm 3.4 (t-HOSVD-ALS): the per-mode ALS + QR of
  * als_sthosvd on the unchanged A for every mode, then
  * G = A x_1 U_1^T ... x_N U_N^T (Section 2, eq. best).  Arguments as for
- * als_sthosvd; opts->order is ignored. */
+ * als_sthosvd; opts->order is ignored.
+ * With opts->singular_vectors != 0 each factor is replaced, before the core
+ * is formed, by the singular vectors of A_(n) inside the span of the QR basis
+ * Q (Section 3, after Algorithm 3.4): U_n = Q W with W the eigenvectors of
+ * the FP64 R_n x R_n Gram Q^T A_(n) A_(n)^T Q of C = Q^T A_(n) (one more pass
+ * over A per mode; Q enters that pass in the compute dtype), columns in
+ * descending order of the singular values, each column of W signed so that
+ * its entry of largest magnitude is positive.  The core is then the one of
+ * these factors.  Singular vectors are unique up to sign only where the
+ * singular values are distinct. */
 TK_API int als_thosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
                const int32_t* ranks, const tk_als_opts* opts, void* const* U,
                void* G, void* ws, size_t ws_bytes, tk_als_info* info,
@@ -263,6 +276,18 @@ TK_API int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t co
 
 TK_API size_t als_sthosvd_batched_workspace_bytes(int32_t count, const int64_t* dims3,
                                            const int32_t* ranks3);
+
+/* --------------------------------------------------------------------------
+ * st_order_auto -- a processing order for als_sthosvd chosen by the cost
+ * model in the proof of Prop. 1 (eq. 2.2): the permutation (i_1, ..., i_N)
+ * minimising sum_n R_{i_1} ... R_{i_n} * I_{i_n} ... I_{i_N} over all N!
+ * orders (exact integer arithmetic), the first in lexicographic order among
+ * equal costs.  With equal dimensions this is the order of ascending ranks
+ * (Prop. 1).  Host only: touches no device and needs no GPU.
+ *  dims   host, int64[N];  ranks host, int32[N] (as for als_sthosvd).
+ *  order  host, int32[N] receives the permutation.
+ * Returns TK_OK or TK_ERR_INVALID_ARG. */
+TK_API int st_order_auto(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t* order);
 
 /* Human-readable name of a tk_status value (static storage). */
 TK_API const char* tk_status_string(int32_t status);

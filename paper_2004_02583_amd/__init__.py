@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import TuckerALSError, load_library  # noqa: F401
 
 __all__ = [
-    "als_sthosvd", "als_thosvd", "ttm", "tucker_reconstruct", "contract_allbut",
+    "als_sthosvd", "als_thosvd", "st_order", "ttm", "tucker_reconstruct", "contract_allbut",
     "als_init_step", "als_sweep_step", "als_sweep_kernel", "qr_f64", "batched_sthosvd",
     "TuckerALSError", "load_library", "TuckerProject", "TuckerReconstruct",
 ]
@@ -47,13 +47,14 @@ def _require_gpu(*ts):
             raise TuckerALSError(-1, "inputs must be contiguous")
 
 
-def _opts(tol, max_iters, seed, order, resid_mode):
+def _opts(tol, max_iters, seed, order, resid_mode, singular_vectors=False):
     o = L.tk_als_opts()
     o.struct_size = ctypes.sizeof(L.tk_als_opts)
     o.tol = float(tol)
     o.max_iters = int(max_iters)
     o.seed = int(seed) & ((1 << 64) - 1)
     o.resid_mode = {"trace": L.TK_RESID_TRACE, "explicit": L.TK_RESID_EXPLICIT}[resid_mode]
+    o.singular_vectors = 1 if singular_vectors else 0
     keep = None
     if order is not None:
         keep = L.i32arr(order)
@@ -72,7 +73,8 @@ def _info_dict(info: L.tk_als_info, N: int) -> dict:
     )
 
 
-def _driver(which, A, ranks, tol, max_iters, seed, order, resid_mode, workspace):
+def _driver(which, A, ranks, tol, max_iters, seed, order, resid_mode, workspace,
+            singular_vectors=False):
     lib = L.lib()
     _require_gpu(A)
     N = A.dim()
@@ -91,7 +93,7 @@ def _driver(which, A, ranks, tol, max_iters, seed, order, resid_mode, workspace)
     ws = workspace
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    o, keep = _opts(tol, max_iters, seed, order, resid_mode)
+    o, keep = _opts(tol, max_iters, seed, order, resid_mode, singular_vectors)
     info = L.tk_als_info()
     fn = lib.als_sthosvd if which == 1 else lib.als_thosvd
     rc = fn(ctypes.c_void_p(A.data_ptr()), adt, N, dims, rk, ctypes.byref(o),
@@ -102,16 +104,33 @@ def _driver(which, A, ranks, tol, max_iters, seed, order, resid_mode, workspace)
     return G, Us, _info_dict(info, N)
 
 
+def st_order(dims, ranks):
+    """Processing order of least eq. 2.2 cost (Prop. 1), computed by the library on the
+    host (no GPU needed)."""
+    lib = L.lib()
+    N = len(dims)
+    out = L.i32arr([0] * N)
+    L.check(lib.st_order_auto(N, L.i64arr(dims), L.i32arr(ranks), out), "st_order_auto")
+    return [int(x) for x in out]
+
+
 def als_sthosvd(A, ranks, tol=1e-4, max_iters=50, seed=0, order=None,
                 resid_mode="trace", workspace=None):
-    """st-HOSVD-ALS (Algorithm 3.5).  Returns (G, [U_n], info)."""
+    """st-HOSVD-ALS (Algorithm 3.5).  Returns (G, [U_n], info).  order: None (natural),
+    a permutation, or "auto" (``st_order``)."""
+    if isinstance(order, str):
+        if order != "auto":
+            raise TuckerALSError(-1, "order must be None, a permutation or 'auto'")
+        order = st_order(list(A.shape), list(ranks))
     return _driver(1, A, list(ranks), tol, max_iters, seed, order, resid_mode, workspace)
 
 
 def als_thosvd(A, ranks, tol=1e-4, max_iters=50, seed=0, resid_mode="trace",
-               workspace=None):
-    """t-HOSVD-ALS (Algorithm 3.4).  Returns (G, [U_n], info)."""
-    return _driver(0, A, list(ranks), tol, max_iters, seed, None, resid_mode, workspace)
+               workspace=None, singular_vectors=False):
+    """t-HOSVD-ALS (Algorithm 3.4).  Returns (G, [U_n], info).  With singular_vectors the
+    factors are the singular vectors of A_(n) inside the ALS subspaces (Section 3)."""
+    return _driver(0, A, list(ranks), tol, max_iters, seed, None, resid_mode, workspace,
+                   singular_vectors)
 
 
 def workspace_bytes(which: str, A_shape, dtype, ranks) -> int:

@@ -28,7 +28,7 @@ EXPORTS = [
     "tucker_reconstruct", "tucker_reconstruct_workspace_bytes",
     "contract_allbut", "contract_allbut_workspace_bytes", "als_init_step",
     "als_sweep_step", "als_sweep_kernel", "qr_f64", "als_sthosvd_batched",
-    "als_sthosvd_batched_workspace_bytes", "tk_status_string",
+    "als_sthosvd_batched_workspace_bytes", "st_order_auto", "tk_status_string",
 ]
 
 
@@ -40,6 +40,7 @@ class tk_als_opts(ctypes.Structure):
         ("resid_mode", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("singular_vectors", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,8 @@ def _declare(lib):
     lib.als_sthosvd_batched.restype = _I32
     lib.als_sthosvd_batched_workspace_bytes.argtypes = [_I32, _PI64, _PI32]
     lib.als_sthosvd_batched_workspace_bytes.restype = _SZ
+    lib.st_order_auto.argtypes = [_I32, _PI64, _PI32, _PI32]
+    lib.st_order_auto.restype = _I32
     lib.tk_status_string.argtypes = [_I32]
     lib.tk_status_string.restype = ctypes.c_char_p
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtucker_als.so")
 SOURCES = ["tk_api.hip", "k_small_la.hip", "k_mode_step.hip", "k_stream.hip", "k_fused.hip",
-           "k_fused_bf16.hip", "k_fused_big.hip", "k_batched.hip"]
+           "k_fused_bf16.hip", "k_fused_big.hip", "k_batched.hip",
+           "k_svec.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

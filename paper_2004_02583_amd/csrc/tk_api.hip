@@ -135,6 +135,7 @@ struct Opts {
   int resid_mode;
   uint64_t seed;
   const int32_t* order;
+  int svec;
 };
 
 int read_opts(const tk_als_opts* o, int N, Opts& out) {
@@ -143,6 +144,7 @@ int read_opts(const tk_als_opts* o, int N, Opts& out) {
   out.resid_mode = TK_RESID_TRACE;
   out.seed = 0;
   out.order = nullptr;
+  out.svec = 0;
   if (!o) return TK_OK;
   if (o->struct_size < sizeof(tk_als_opts)) return TK_ERR_INVALID_ARG;
   if (!(o->tol >= 0.0) || o->max_iters < 0) return TK_ERR_INVALID_ARG;
@@ -153,6 +155,7 @@ int read_opts(const tk_als_opts* o, int N, Opts& out) {
   out.resid_mode = o->resid_mode;
   out.seed = o->seed;
   out.order = o->order;
+  out.svec = o->singular_vectors != 0;
   if (out.order) {
     bool seen[TK_MAX_ORDER] = {false};
     for (int k = 0; k < N; ++k) {
@@ -372,6 +375,44 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
   return h.status;
 }
 
+// Singular vectors of X_(mode) inside the span of the orthonormal Q (FP64 I x R;
+// Section 3, after Algorithm 3.4): M = Q^T X_(mode) X_(mode)^T Q from one streaming
+// pass with Q (in the compute dtype) as L~, its eigenvectors W (FP64 Jacobi) into w.CL,
+// and Q W into w.Lnext.
+int svec_enqueue(const void* X, int xdt, const View& v, int R, const double* Q, ModeWs& w,
+                 hipStream_t s) {
+  const int64_t IR = v.I * (int64_t)R;
+  const int64_t RR = (int64_t)R * R;
+  const int cdt = cdtype(xdt);
+  if (cdt == TK_F64) launch_convert<double>(Q, IR, (double*)w.Lq, s);
+  else launch_convert<float>(Q, IR, (float*)w.Lq, s);
+  if (fused_supported(xdt, v, R, TK_RESID_TRACE)) {
+    FusedArgs f{};
+    f.X = X; f.x_dtype = xdt; f.v = v; f.R = R;
+    f.Lq = (const float*)w.Lq;
+    f.lacc_parts = (float*)w.parts;
+    f.gv_parts = w.gparts;
+    int nwg = launch_fused(f, NWG_MAX, s);
+    launch_reduce_parts<double>(w.gparts, FUSED_WAVES * nwg, RR, RR, w.GV, w.rtmp, s);
+  } else {
+    VpassArgs a{};
+    a.X = X; a.x_dtype = xdt; a.v = v;
+    a.W = w.Lq; a.w_ldi = R; a.w_ldo = 1; a.O = R;
+    a.out = w.V; a.out_kind = 0;
+    int nres = 0;
+    launch_vpass(a, NWG_MAX, &nres, s);
+    int gch = (int)std::min<int64_t>(NWG_MAX, std::max<int64_t>(1, ceil_div(v.J(), 4096)));
+    launch_gram_parts(w.V, cdt, v.J(), R, gch, w.gparts, s);
+    launch_reduce_parts<double>(w.gparts, gch, RR, RR, w.GV, w.rtmp, s);
+  }
+  launch_sym_eig(w.GV, R, w.CL, w.Wq, &w.st->status, s);
+  launch_rotate(Q, v.I, R, w.CL, w.Lnext, s);
+  DevStatus h{};
+  int rc = read_status(w.st, &h, s);
+  if (rc) return rc;
+  return h.status;
+}
+
 // ---------------------------------------------------------------------------
 // Workspace plan of the drivers.
 
@@ -497,10 +538,19 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
       return rc;
     }
     if (!mr.converged) worst = TK_NOT_CONVERGED;
+    const double* Uf = U64[n];
+    if (which == 0 && o.svec) {
+      rc = svec_enqueue(A, adt, v, R, U64[n], w, s);
+      if (rc) {
+        if (info) info->status = rc;
+        return rc;
+      }
+      Uf = w.Lnext;
+    }
     // factor in the caller's dtype
     const int64_t IR = v.I * (int64_t)R;
-    if (cdt == TK_F64) launch_convert<double>(U64[n], IR, (double*)U[n], s);
-    else launch_convert<float>(U64[n], IR, (float*)U[n], s);
+    if (cdt == TK_F64) launch_convert<double>(Uf, IR, (double*)U[n], s);
+    else launch_convert<float>(Uf, IR, (float*)U[n], s);
     if (which == 1) {
       // B <- B x_n U_n^T (equals Algorithm 3.5's R_hat R^T)
       void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
@@ -547,6 +597,32 @@ const char* tk_status_string(int32_t st) {
     case TK_ERR_HIP: return "TK_ERR_HIP";
   }
   return "TK_UNKNOWN_STATUS";
+}
+
+int st_order_auto(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t* order) {
+  if (!order || !valid_dims(N, dims) || !valid_ranks(N, dims, ranks)) return TK_ERR_INVALID_ARG;
+  // each term is below 64^8 * 2^63 and there are at most 8 of them
+  using u128 = unsigned __int128;
+  int perm[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) perm[k] = k;
+  u128 best = 0;
+  bool have = false;
+  do {
+    u128 cost = 0;
+    for (int n = 0; n < N; ++n) {
+      u128 r = 1, i = 1;
+      for (int k = 0; k <= n; ++k) r *= (u128)ranks[perm[k]];
+      for (int k = n; k < N; ++k) i *= (u128)dims[perm[k]];
+      cost += r * i;
+    }
+    // permutations come in lexicographic order: keep the first of equal cost
+    if (!have || cost < best) {
+      best = cost;
+      have = true;
+      for (int k = 0; k < N; ++k) order[k] = perm[k];
+    }
+  } while (std::next_permutation(perm, perm + N));
+  return TK_OK;
 }
 
 size_t als_workspace_bytes(int32_t which, int32_t a_dtype, int32_t N, const int64_t* dims,

@@ -36,6 +36,16 @@ void launch_identity(T* U, int64_t n, hipStream_t s);
 template <typename T>
 void launch_convert(const double* in, int64_t n, T* out, hipStream_t s);
 
+// Singular vectors within an orthonormal basis (Section 3, after Algorithm 3.4).
+// launch_sym_eig: eigenvectors W (r x r row-major, descending eigenvalues, each column's
+// largest-magnitude entry positive) and eigenvalues of the symmetric FP64 r x r matrix M,
+// r <= 64, by cyclic Jacobi in one workgroup; *status = TK_ERR_NONFINITE on Inf/NaN.
+// launch_rotate: out = Q W, Q m x r, W r x r, out m x r, all FP64 row-major.
+void launch_sym_eig(const double* M, int r, double* W, double* evals, int* status,
+                    hipStream_t s);
+void launch_rotate(const double* Q, int64_t m, int r, const double* W, double* out,
+                   hipStream_t s);
+
 // ---------------------------------------------------------------- streaming
 // Contraction over the mode index (generic VALU path):
 //   out(j, o) = sum_i W(i, o) X[p, i, q],  j = p*Q + q,  0 <= o < O

@@ -158,3 +158,31 @@ def test_product_path_does_not_touch_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.replace("oracle-free", ""), f
+
+
+def test_st_order_auto_host(lib):
+    """The automatic st-HOSVD order is host logic: it runs without a GPU and equals the
+    oracle's exhaustive eq. 2.2 minimiser (integers, compared exactly)."""
+    from oracle import tucker_oracle as o
+    rng = __import__("numpy").random.default_rng(60)
+    for N in (1, 2, 3, 4, 5, 6):
+        for _ in range(6):
+            dims = [int(x) for x in rng.integers(2, 200, N)]
+            while True:
+                ranks = [int(rng.integers(1, min(d, 64) + 1)) for d in dims]
+                others_ok = all(N == 1 or ranks[n] <= int(__import__("numpy").prod(
+                    [ranks[k] for k in range(N) if k != n])) for n in range(N))
+                if others_ok:
+                    break
+            out = L.i32arr([0] * N)
+            assert lib.st_order_auto(N, L.i64arr(dims), L.i32arr(ranks), out) == 0
+            assert list(out) == o.st_order_auto(dims, ranks), (dims, ranks)
+    out = L.i32arr([0] * 3)
+    assert lib.st_order_auto(3, L.i64arr((8, 9, 10)), L.i32arr((9, 3, 4)), out) == -1
+    assert lib.st_order_auto(3, L.i64arr((8, 9, 10)), L.i32arr((2, 3, 4)), None) == -1
+    assert lib.st_order_auto(0, L.i64arr((8,)), L.i32arr((2,)), out) == -1
+    # largest shape the library accepts: 8 modes, ranks 64, no overflow of the cost
+    big = [230] * 8
+    out8 = L.i32arr([0] * 8)
+    assert lib.st_order_auto(8, L.i64arr(big), L.i32arr([64] * 7 + [63]), out8) == 0
+    assert list(out8) == o.st_order_auto(big, [64] * 7 + [63])
