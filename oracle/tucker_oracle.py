@@ -476,6 +476,36 @@ def sthosvd_svd(A: np.ndarray, ranks, order=None, method: str = "auto"):
     return TuckerResult(B, Us, [], frob(A)), disc
 
 
+def hooi(A: np.ndarray, Us0, tol: float = 1e-12, max_iters: int = 50):
+    """HOOI, the higher-order orthogonal iteration (De Lathauwer, De Moor and
+    Vandewalle 2000; the refinement the paper runs from t-/st-HOSVD results,
+    Section 6.3, Table 6.3-2), from the orthonormal factors Us0.  One outer
+    iteration sets, for n = 0..N-1 in turn, U_n to the leading R_n left
+    singular vectors of Y_(n) with Y = A x_{k != n} U_k^T; then
+    G = A x_1 U_1^T ... x_N U_N^T and e = ||A - A_hat|| / ||A|| (explicit
+    reconstruction).  Stops when |e_prev - e| <= tol.
+    Returns (G, Us, errors, converged); errors[0] is the error of Us0."""
+    A = np.asarray(A, dtype=np.float64)
+    N = A.ndim
+    Us = [np.array(U, dtype=np.float64) for U in Us0]
+    G = core_from_factors(A, Us)
+    errs = [relerr(A, G, Us)]
+    converged = max_iters == 0
+    for _ in range(max_iters):
+        for n in range(N):
+            Y = A
+            for k in range(N):
+                if k != n:
+                    Y = ttm(Y, Us[k].T, k)
+            Us[n] = leading_left_singular_vectors(unfold(Y, n), Us[n].shape[1])
+        G = core_from_factors(A, Us)
+        errs.append(relerr(A, G, Us))
+        if abs(errs[-2] - errs[-1]) <= tol:
+            converged = True
+            break
+    return G, Us, errs, converged
+
+
 def tail_energies(A: np.ndarray, ranks):
     """gamma_n = sum_{r > R_n} sigma_r(A_(n))^2 (Lemma 2, eq. E5.1)."""
     return [float(np.sum(singular_values(unfold(A, n))[ranks[n]:] ** 2))

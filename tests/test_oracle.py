@@ -426,6 +426,54 @@ def test_st_order_auto_prop1_and_ties():
         assert tuple(best) == min(p for p, c in costs.items() if c == m)
 
 
+def _hooi_stationarity(A, Us):
+    """max_n ||(I - U_n U_n^T) Y_(n) Y_(n)^T U_n|| / ||Y||^2, Y = A x_{k != n} U_k^T: zero
+    at a stationary point of ||G||^2 over orthonormal factors (first-order condition)."""
+    worst = 0.0
+    for n in range(A.ndim):
+        Y = A
+        for k in range(A.ndim):
+            if k != n:
+                Y = o.ttm(Y, Us[k].T, k)
+        Yn = o.unfold(Y, n)
+        M = Yn @ Yn.T
+        U = Us[n]
+        worst = max(worst, np.linalg.norm(M @ U - U @ (U.T @ M @ U)) / np.linalg.norm(M))
+    return worst
+
+
+def test_hooi_monotone_stationary_and_bounded():
+    """HOOI from t-HOSVD on a noisy tensor: the error never increases, ends strictly below
+    the t-HOSVD error, is bounded below by every single-mode Eckart-Young error, and the
+    final factors satisfy the first-order stationarity condition."""
+    rng = np.random.default_rng(35)
+    dims, ranks = (14, 12, 10), (4, 3, 3)
+    A = synth.tucker_lowrank(rng, dims, ranks, 0.3)[0]
+    start = o.thosvd_svd(A, ranks)
+    G, Us, errs, conv = o.hooi(A, start.U, tol=1e-13, max_iters=500)
+    assert conv
+    assert all(b <= a * (1 + 1e-13) for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < errs[0] - 1e-6
+    nA = o.frob(A)
+    gam = o.tail_energies(A, ranks)
+    assert errs[-1] * nA >= max(gam) ** 0.5 * (1 - 1e-12)
+    assert _hooi_stationarity(A, Us) < 1e-6
+    # the t-HOSVD start itself is not stationary here
+    assert _hooi_stationarity(A, start.U) > 1e-4
+    for U in Us:
+        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-13)
+
+
+def test_hooi_recovers_exact_low_rank_from_random_start():
+    rng = np.random.default_rng(36)
+    dims, ranks = (10, 9, 8), (3, 2, 3)
+    A = synth.tucker_lowrank(rng, dims, ranks, 0.0)[0]
+    Us0 = [synth.orthonormal(rng, d, r) for d, r in zip(dims, ranks)]
+    G, Us, errs, conv = o.hooi(A, Us0, tol=1e-15, max_iters=200)
+    assert errs[0] > 0.1
+    assert errs[-1] < 1e-7
+
+
 # ---------------------------------------------------------- P8: gradients
 
 def _fd(f, x, d, h=1e-3):
