@@ -278,6 +278,47 @@ TK_API size_t als_sthosvd_batched_workspace_bytes(int32_t count, const int64_t* 
                                            const int32_t* ranks3);
 
 /* --------------------------------------------------------------------------
+ * hooi_refine -- HOOI (higher-order orthogonal iteration) started from the
+ * caller's factors, the refinement the paper applies to t-/st-HOSVD results
+ * (Section 6.3, Table 6.3-2).  One outer iteration updates, for n = 0..N-1
+ * in turn, U_n to an orthonormal basis of the dominant R_n-dimensional left
+ * subspace of Y_(n), Y = A x_{k != n} U_k^T: ALS (Algorithm 3.3, options from
+ * opts: tol, max_iters, resid_mode; the E5.01 test against ||A||_F) on Y_(n),
+ * warm-started from the current U_n, then the reduced QR (diag(R_hat) > 0).
+ * After the last mode G = Y x_{N-1} U_{N-1}^T and the error
+ * e = sqrt(||A||^2 - ||G||^2) / ||A|| (orthonormal factors); the iteration
+ * stops when |e_prev - e| <= tol, e_prev starting at the error of the given
+ * factors.
+ *  A      device, input tensor (dtype a_dtype), as for als_thosvd.
+ *  U      host array of N device pointers, in/out: I_n x R_n row-major with
+ *         orthonormal columns on entry (FP64 when a_dtype == TK_F64, else
+ *         FP32), overwritten by the refined factors.
+ *  G      device, R_1 x ... x R_N, same dtype as U: the core of the result.
+ *  tol    >= 0, stop tolerance on the change of e.  max_iters >= 0 outer
+ *         iterations (0: only the error of the given factors and their core).
+ *  ws     device workspace of ws_bytes >= hooi_workspace_bytes(...).
+ *  info   host or NULL.
+ * Returns TK_OK, TK_NOT_CONVERGED (max_iters reached) or a negative
+ * tk_status. */
+typedef struct {
+  int32_t iters;       /* outer iterations performed                        */
+  int32_t converged;   /* 1 if |e_prev - e| <= tol was reached               */
+  double relerr_init;  /* e of the given factors                             */
+  double relerr;       /* e of the returned factors                          */
+  double norm_a;       /* ||A||_F                                           */
+  int32_t sweeps;      /* ALS sweeps over all inner solves                   */
+  int32_t status;      /* same as the return value                          */
+} tk_hooi_info;
+
+TK_API int hooi_refine(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                       const int32_t* ranks, const tk_als_opts* opts, double tol,
+                       int32_t max_iters, void* const* U, void* G, void* ws,
+                       size_t ws_bytes, tk_hooi_info* info, void* stream);
+
+TK_API size_t hooi_workspace_bytes(int32_t a_dtype, int32_t N, const int64_t* dims,
+                                   const int32_t* ranks);
+
+/* --------------------------------------------------------------------------
  * st_order_auto -- a processing order for als_sthosvd chosen by the cost
  * model in the proof of Prop. 1 (eq. 2.2): the permutation (i_1, ..., i_N)
  * minimising sum_n R_{i_1} ... R_{i_n} * I_{i_n} ... I_{i_N} over all N!

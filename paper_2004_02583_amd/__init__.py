@@ -17,7 +17,7 @@ from . import _lib as L
 from ._lib import TuckerALSError, load_library  # noqa: F401
 
 __all__ = [
-    "als_sthosvd", "als_thosvd", "st_order", "ttm", "tucker_reconstruct", "contract_allbut",
+    "als_sthosvd", "als_thosvd", "hooi", "st_order", "ttm", "tucker_reconstruct", "contract_allbut",
     "als_init_step", "als_sweep_step", "als_sweep_kernel", "qr_f64", "batched_sthosvd",
     "TuckerALSError", "load_library", "TuckerProject", "TuckerReconstruct",
 ]
@@ -131,6 +131,48 @@ def als_thosvd(A, ranks, tol=1e-4, max_iters=50, seed=0, resid_mode="trace",
     factors are the singular vectors of A_(n) inside the ALS subspaces (Section 3)."""
     return _driver(0, A, list(ranks), tol, max_iters, seed, None, resid_mode, workspace,
                    singular_vectors)
+
+
+def hooi(A, factors, tol=1e-10, max_iters=50, als_tol=1e-8, als_max_iters=50, seed=0,
+         resid_mode="trace", workspace=None):
+    """HOOI refinement (Section 6.3) started from ``factors`` (orthonormal I_n x R_n
+    tensors, left unchanged).  Returns (G, [U_n], info) with the refined factors;
+    als_tol / als_max_iters drive the warm-started inner ALS."""
+    lib = L.lib()
+    _require_gpu(A)
+    N = A.dim()
+    if len(factors) != N:
+        raise TuckerALSError(-1, "one factor per mode")
+    ranks = [int(U.shape[1]) for U in factors]
+    dims = L.i64arr(A.shape)
+    rk = L.i32arr(ranks)
+    adt = _dtcode(A)
+    need = lib.hooi_workspace_bytes(adt, N, dims, rk)
+    if need == 0:
+        raise TuckerALSError(-1, "hooi_workspace_bytes")
+    fdt = _factor_dtype(A.dtype)
+    dev = A.device
+    Us = []
+    for n, U in enumerate(factors):
+        _require_gpu(U)
+        if tuple(U.shape) != (A.shape[n], ranks[n]):
+            raise TuckerALSError(-1, "factor shape")
+        Us.append(U.to(fdt).clone().contiguous())
+    G = torch.empty(tuple(ranks), dtype=fdt, device=dev)
+    ws = workspace
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    o, keep = _opts(als_tol, als_max_iters, seed, None, resid_mode)
+    info = L.tk_hooi_info()
+    rc = lib.hooi_refine(ctypes.c_void_p(A.data_ptr()), adt, N, dims, rk, ctypes.byref(o),
+                         float(tol), int(max_iters), L.ptrarr([u.data_ptr() for u in Us]),
+                         ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                         ws.numel(), ctypes.byref(info), _stream(dev))
+    del keep
+    L.check(rc, "hooi_refine", allow=(0, 1))
+    return G, Us, dict(iters=info.iters, converged=bool(info.converged),
+                       relerr_init=info.relerr_init, relerr=info.relerr, norm_a=info.norm_a,
+                       sweeps=info.sweeps, status=L.STATUS.get(info.status, info.status))
 
 
 def workspace_bytes(which: str, A_shape, dtype, ranks) -> int:

@@ -28,7 +28,8 @@ EXPORTS = [
     "tucker_reconstruct", "tucker_reconstruct_workspace_bytes",
     "contract_allbut", "contract_allbut_workspace_bytes", "als_init_step",
     "als_sweep_step", "als_sweep_kernel", "qr_f64", "als_sthosvd_batched",
-    "als_sthosvd_batched_workspace_bytes", "st_order_auto", "tk_status_string",
+    "als_sthosvd_batched_workspace_bytes", "hooi_refine", "hooi_workspace_bytes",
+    "st_order_auto", "tk_status_string",
 ]
 
 
@@ -49,6 +50,18 @@ class tk_als_info(ctypes.Structure):
         ("iters", ctypes.c_int32 * TK_MAX_ORDER),
         ("converged", ctypes.c_int32 * TK_MAX_ORDER),
         ("resid", ctypes.c_double * TK_MAX_ORDER),
+        ("norm_a", ctypes.c_double),
+        ("sweeps", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class tk_hooi_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("relerr_init", ctypes.c_double),
+        ("relerr", ctypes.c_double),
         ("norm_a", ctypes.c_double),
         ("sweeps", ctypes.c_int32),
         ("status", ctypes.c_int32),
@@ -109,6 +122,12 @@ def _declare(lib):
     lib.als_sthosvd_batched.restype = _I32
     lib.als_sthosvd_batched_workspace_bytes.argtypes = [_I32, _PI64, _PI32]
     lib.als_sthosvd_batched_workspace_bytes.restype = _SZ
+    lib.hooi_refine.argtypes = [_P, _I32, _I32, _PI64, _PI32, ctypes.POINTER(tk_als_opts),
+                                ctypes.c_double, _I32, ctypes.POINTER(_P), _P, _P, _SZ,
+                                ctypes.POINTER(tk_hooi_info), _P]
+    lib.hooi_refine.restype = _I32
+    lib.hooi_workspace_bytes.argtypes = [_I32, _I32, _PI64, _PI32]
+    lib.hooi_workspace_bytes.restype = _SZ
     lib.st_order_auto.argtypes = [_I32, _PI64, _PI32, _PI32]
     lib.st_order_auto.restype = _I32
     lib.tk_status_string.argtypes = [_I32]

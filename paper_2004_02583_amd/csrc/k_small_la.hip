@@ -56,6 +56,12 @@ __global__ void k_convert(const double* __restrict__ in, int64_t n, T* __restric
   if (e < n) out[e] = Store<T>::cvt(in[e]);
 }
 
+template <typename T>
+__global__ void k_widen(const T* __restrict__ in, int64_t n, double* __restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = (double)in[e];
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 
@@ -93,5 +99,12 @@ void launch_convert(const double* in, int64_t n, T* out, hipStream_t s) {
 }
 template void launch_convert<double>(const double*, int64_t, double*, hipStream_t);
 template void launch_convert<float>(const double*, int64_t, float*, hipStream_t);
+
+template <typename T>
+void launch_widen(const T* in, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_widen<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, in, n, out);
+}
+template void launch_widen<double>(const double*, int64_t, double*, hipStream_t);
+template void launch_widen<float>(const float*, int64_t, double*, hipStream_t);
 
 }  // namespace tk

@@ -322,10 +322,12 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
 // input tensor; norm_a < 0: the norm of X).  normx2 = ||X||_F^2 of the
 // tensor being swept (trace form of the residual); when it is negative on
 // entry the initial pass computes it and returns it there.  On return U64
-// (FP64 I x R) holds Q of the reduced QR of the returned L.
+// (FP64 I x R) holds Q of the reduced QR of the returned L.  With L0 (FP64
+// I x R, device; may alias U64) the iteration starts from L0 instead of the
+// sketch (a warm start), and ||X||^2 comes from a pass of its own.
 int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, double& normx2,
                double norm_a, int mode, ModeWs& w, double* U64, ModeResult& mr,
-               hipStream_t s) {
+               hipStream_t s, const double* L0 = nullptr) {
   mr.iters = 0; mr.converged = 1; mr.sweeps = 0; mr.resid = 0.0;
   DevStatus h{};
   const bool want_norm = normx2 < 0.0;
@@ -341,7 +343,12 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
     launch_identity<double>(U64, v.I, s);
     return TK_OK;
   }
-  init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, want_norm ? &w.st->norm2 : nullptr, s);
+  if (L0) {
+    if (want_norm) norm2_enqueue(X, xdt, v.P * v.I * v.Q, w.sparts, &w.st->norm2, w.rtmp, s);
+    HIPCHK(hipMemcpyAsync(w.Lacc, L0, (size_t)v.I * R * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, want_norm ? &w.st->norm2 : nullptr, s);
+  }
   init_finish_enqueue(v, R, xdt, o.resid_mode, w, s);
   int rc = read_status(w.st, &h, s);
   if (rc) return rc;
@@ -578,6 +585,165 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   return worst;
 }
 
+// Workspace of hooi_refine: that of st-HOSVD-ALS (whose bound covers every mode
+// solve on the truncated tensors Y of either dtype) and one status block.
+size_t hooi_ws(int xdt, int N, const int64_t* dims, const int32_t* ranks) {
+  return driver_ws(1, xdt, N, dims, ranks) + align_up(sizeof(DevStatus)) + 4096;
+}
+
+// G = A x_1 U_1^T ... x_N U_N^T through the ping-pong buffers; returns the status of
+// the TTM launches.
+int core_chain(const void* A, int adt, int N, const int64_t* dims, const int32_t* ranks,
+               void* const* U, void* G, void* bufA, void* bufB, hipStream_t s) {
+  int64_t cur[TK_MAX_ORDER];
+  for (int k = 0; k < N; ++k) cur[k] = dims[k];
+  const void* B = A;
+  int bdt = adt;
+  for (int t = 0; t < N; ++t) {
+    void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
+    int rc = ttm_enqueue(B, bdt, N, cur, t, U[t], ranks[t], 1, dst, s);
+    if (rc) return rc;
+    cur[t] = ranks[t];
+    B = dst;
+    bdt = cdtype(adt);
+  }
+  return TK_OK;
+}
+
+// HOOI (higher-order orthogonal iteration) from the caller's orthonormal factors, the
+// refinement the paper applies to t-/st-HOSVD(-ALS) results (Section 6.3, Table 6.3-2).
+// An outer iteration replaces, for n = 0..N-1 in turn, U_n by an orthonormal basis of
+// the dominant R_n-dimensional left subspace of Y_(n), Y = A x_{k != n} U_k^T: ALS
+// (Algorithm 3.3) on Y_(n) warm-started from U_n, then QR.  The core is
+// G = Y x_{N-1} U_{N-1}^T of the last mode, and the error
+// ||A - A_hat|| / ||A|| = sqrt(||A||^2 - ||G||^2) / ||A|| (orthonormal factors); the
+// iteration stops when it changes by at most tol.
+int run_hooi(const void* A, int32_t adt, int32_t N, const int64_t* dims, const int32_t* ranks,
+             const tk_als_opts* opts, double tol, int32_t max_iters, void* const* U, void* G,
+             void* ws, size_t ws_bytes, tk_hooi_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (!valid_dtype(adt)) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A || !U || !G || !valid_dims(N, dims) || !valid_ranks(N, dims, ranks) ||
+      !(tol >= 0.0) || max_iters < 0)
+    return TK_ERR_INVALID_ARG;
+  for (int n = 0; n < N; ++n)
+    if (!U[n]) return TK_ERR_INVALID_ARG;
+  Opts o;
+  int rc = read_opts(opts, N, o);
+  if (rc) return rc;
+  const size_t need = hooi_ws(adt, N, dims, ranks);
+  if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
+
+  hipStream_t s = (hipStream_t)stream;
+  const int cdt = cdtype(adt);
+  const size_t cs = dsize(cdt);
+  const int64_t ech = chain_elems(N, dims, ranks);
+  Arena ar(ws, ws_bytes);
+  void* bufA = ar.take(ech * cs);
+  void* bufB = ar.take(ech * cs);
+  double* U64[TK_MAX_ORDER];
+  for (int n = 0; n < N; ++n) U64[n] = (double*)ar.take((size_t)dims[n] * ranks[n] * 8);
+  DevStatus* hs = (DevStatus*)ar.take(sizeof(DevStatus));
+  Arena mar(ar.base + ar.off, ar.cap - ar.off);
+  int64_t gsize = 1;
+  for (int n = 0; n < N; ++n) gsize *= ranks[n];
+
+  for (int n = 0; n < N; ++n) {
+    const int64_t IR = dims[n] * (int64_t)ranks[n];
+    if (cdt == TK_F64) launch_widen<double>((const double*)U[n], IR, U64[n], s);
+    else launch_widen<float>((const float*)U[n], IR, U64[n], s);
+  }
+  // ||A||^2, then the error of the starting factors
+  DevStatus h{};
+  {
+    Arena tmp = mar;
+    ModeWs w;
+    carve_mode(tmp, adt, mode_view(N, dims, 0), ranks[0], w);
+    HIPCHK(hipMemsetAsync(hs, 0, sizeof(DevStatus), s));
+    norm2_enqueue(A, adt, numel(N, dims), w.sparts, &hs->norm2, w.rtmp, s);
+    rc = read_status(hs, &h, s);
+    if (rc) return rc;
+  }
+  const double nA2 = h.norm2;
+  if (!isfinite(nA2)) return TK_ERR_NONFINITE;
+  const double nA = sqrt(nA2);
+  if (info) info->norm_a = nA;
+  auto error_of_core = [&](double& err) -> int {
+    Arena tmp = mar;
+    ModeWs w;
+    carve_mode(tmp, adt, mode_view(N, dims, 0), ranks[0], w);
+    norm2_enqueue(G, cdt, gsize, w.sparts, &hs->norm2, w.rtmp, s);
+    int r2 = read_status(hs, &h, s);
+    if (r2) return r2;
+    if (!isfinite(h.norm2)) return TK_ERR_NONFINITE;
+    const double d = nA2 - h.norm2;
+    err = nA2 > 0.0 ? sqrt(d > 0.0 ? d : 0.0) / nA : 0.0;
+    return TK_OK;
+  };
+  rc = core_chain(A, adt, N, dims, ranks, U, G, bufA, bufB, s);
+  if (rc) return rc;
+  double err_prev = 0.0;
+  rc = error_of_core(err_prev);
+  if (rc) return rc;
+  if (info) { info->relerr_init = err_prev; info->relerr = err_prev; }
+
+  int result = TK_NOT_CONVERGED;
+  for (int it = 1; it <= max_iters; ++it) {
+    for (int n = 0; n < N; ++n) {
+      // Y = A x_{k != n} U_k^T
+      int64_t cur[TK_MAX_ORDER];
+      for (int k = 0; k < N; ++k) cur[k] = dims[k];
+      const void* B = A;
+      int bdt = adt;
+      int t = 0;
+      for (int k = 0; k < N; ++k) {
+        if (k == n) continue;
+        void* dst = (t % 2 == 0) ? bufA : bufB;
+        rc = ttm_enqueue(B, bdt, N, cur, k, U[k], ranks[k], 1, dst, s);
+        if (rc) return rc;
+        cur[k] = ranks[k];
+        B = dst;
+        bdt = cdt;
+        ++t;
+      }
+      const View v = mode_view(N, cur, n);
+      const int R = ranks[n];
+      Arena tmp = mar;
+      ModeWs w;
+      carve_mode(tmp, bdt, v, R, w);
+      ModeResult mr;
+      double ny2 = -1.0;
+      rc = mode_solve(B, bdt, v, R, o, ny2, nA, n, w, U64[n], mr, s, U64[n]);
+      if (info) info->sweeps += mr.sweeps;
+      if (rc < 0) {
+        if (info) info->status = rc;
+        return rc;
+      }
+      const int64_t IR = v.I * (int64_t)R;
+      if (cdt == TK_F64) launch_convert<double>(U64[n], IR, (double*)U[n], s);
+      else launch_convert<float>(U64[n], IR, (float*)U[n], s);
+      if (n == N - 1) {
+        rc = ttm_enqueue(B, bdt, N, cur, n, U[n], R, 1, G, s);
+        if (rc) return rc;
+      }
+    }
+    double err = 0.0;
+    rc = error_of_core(err);
+    if (rc) return rc;
+    if (info) { info->iters = it; info->relerr = err; }
+    if (fabs(err_prev - err) <= tol) {
+      result = TK_OK;
+      break;
+    }
+    err_prev = err;
+  }
+  if (max_iters == 0) result = TK_OK;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  if (info) { info->converged = result == TK_OK; info->status = result; }
+  return result;
+}
+
 }  // namespace
 }  // namespace tk
 
@@ -597,6 +763,20 @@ const char* tk_status_string(int32_t st) {
     case TK_ERR_HIP: return "TK_ERR_HIP";
   }
   return "TK_UNKNOWN_STATUS";
+}
+
+int hooi_refine(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                const int32_t* ranks, const tk_als_opts* opts, double tol, int32_t max_iters,
+                void* const* U, void* G, void* ws, size_t ws_bytes, tk_hooi_info* info,
+                void* stream) {
+  return run_hooi(A, a_dtype, N, dims, ranks, opts, tol, max_iters, U, G, ws, ws_bytes, info,
+                  stream);
+}
+
+size_t hooi_workspace_bytes(int32_t a_dtype, int32_t N, const int64_t* dims,
+                            const int32_t* ranks) {
+  if (!valid_dtype(a_dtype) || !valid_dims(N, dims) || !valid_ranks(N, dims, ranks)) return 0;
+  return hooi_ws(a_dtype, N, dims, ranks);
 }
 
 int st_order_auto(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t* order) {

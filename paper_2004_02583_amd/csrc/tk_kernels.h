@@ -35,6 +35,8 @@ template <typename T>
 void launch_identity(T* U, int64_t n, hipStream_t s);
 template <typename T>
 void launch_convert(const double* in, int64_t n, T* out, hipStream_t s);
+template <typename T>
+void launch_widen(const T* in, int64_t n, double* out, hipStream_t s);
 
 // Singular vectors within an orthonormal basis (Section 3, after Algorithm 3.4).
 // launch_sym_eig: eigenvectors W (r x r row-major, descending eigenvalues, each column's

@@ -186,3 +186,26 @@ def test_st_order_auto_host(lib):
     out8 = L.i32arr([0] * 8)
     assert lib.st_order_auto(8, L.i64arr(big), L.i32arr([64] * 7 + [63]), out8) == 0
     assert list(out8) == o.st_order_auto(big, [64] * 7 + [63])
+
+
+def test_hooi_validation(lib):
+    """hooi_refine rejects bad arguments before any device work."""
+    dims, ranks = L.i64arr((8, 9, 10)), L.i32arr((2, 3, 4))
+    U = L.ptrarr([0x100000] * 3)
+
+    def call(adt=1, A=FAKE, N=3, d=dims, r=ranks, tol=1e-8, it=5, U=U, G=FAKE, ws=FAKE,
+             wsb=1 << 30):
+        return lib.hooi_refine(A, adt, N, d, r, None, tol, it, U, G, ws, wsb, None, None)
+    assert call(adt=7) == -2
+    assert call(A=None) == -1
+    assert call(G=None) == -1
+    assert call(U=L.ptrarr([0x100000, 0, 0x100000])) == -1
+    assert call(tol=-1.0) == -1
+    assert call(tol=float("nan")) == -1
+    assert call(it=-1) == -1
+    assert call(r=L.i32arr((9, 3, 4))) == -1
+    assert call(wsb=16) == -3
+    assert call(ws=None) == -3
+    need = lib.hooi_workspace_bytes(1, 3, dims, ranks)
+    assert need >= lib.als_workspace_bytes(1, 1, 3, dims, ranks)
+    assert lib.hooi_workspace_bytes(1, 3, dims, L.i32arr((9, 3, 4))) == 0
