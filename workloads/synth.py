@@ -15,6 +15,15 @@ Recipe (noise is relative: the noise tensor E is rescaled so that
 * ``cp_lowrank``: the CP-model experiment of Section 6.1.1, lambda_r in
   U[5,10] and unit-norm random vectors, plus relative noise.
 
+* ``cp_paper`` / ``tucker_paper`` (and their ``_torch`` device versions): the
+  two experiments of Section 6.1 as the paper states them: A_hat = A + delta E
+  with E i.i.d. N(0,1) and ABSOLUTE noise level delta = 1e-4; the CP model of
+  Section 6.1.1 on I x I x 100I with R = 0.2 I terms, lambda_r ~ U[5,10] and
+  unit-norm Gaussian vectors; the Tucker model of Section 6.1.2 on
+  I x 100 x 100 x 100 with core (0.01 I, 10, 10, 10) ~ U[5,10] and orthonormal
+  factors.  Both return (A_hat, A): the paper measures errors against the
+  noise-free A.
+
 Seeds: ``2004025830 + k`` for the k-th named workload.
 """
 from __future__ import annotations
@@ -94,6 +103,40 @@ def cp_lowrank(rng: np.random.Generator, dims, rank: int, noise_rel: float):
         E *= noise_rel * np.linalg.norm(A0.ravel()) / np.linalg.norm(E.ravel())
         A = A0 + E
     return A, A0
+
+
+def _cp_terms(rng, dims, rank):
+    lam = rng.uniform(5.0, 10.0, size=rank)
+    vecs = []
+    for d in dims:
+        V = rng.standard_normal((d, rank))
+        vecs.append(V / np.linalg.norm(V, axis=0, keepdims=True))
+    return lam, vecs
+
+
+def cp_paper(rng: np.random.Generator, I: int, rank: int | None = None, delta: float = 1e-4,
+             K: int | None = None):
+    """Section 6.1.1: dims (I, I, K = 100 I), R = 0.2 I rank-one terms, absolute noise
+    delta * N(0,1).  Returns (A_hat, A) in float64."""
+    R = rank if rank is not None else max(1, int(round(0.2 * I)))
+    dims = (I, I, K if K is not None else 100 * I)
+    lam, (a, b, c) = _cp_terms(rng, dims, R)
+    A = np.einsum("r,ir,jr,kr->ijk", lam, a, b, c, optimize=True)
+    return A + delta * rng.standard_normal(dims), A
+
+
+def tucker_paper(rng: np.random.Generator, I: int, J: int = 100, delta: float = 1e-4,
+                 R1: int | None = None, R: int = 10):
+    """Section 6.1.2: dims (I, J, J, J) with J = 100, core (R1 = 0.01 I, R, R, R) with
+    U[5,10] entries, orthonormal factors, absolute noise delta * N(0,1).
+    Returns (A_hat, A) in float64."""
+    core = (R1 if R1 is not None else max(1, int(round(0.01 * I))), R, R, R)
+    dims = (I, J, J, J)
+    G = rng.uniform(5.0, 10.0, size=core)
+    A = G
+    for n in range(4):
+        A = _mode_product(A, orthonormal(rng, dims[n], core[n]), n)
+    return A + delta * rng.standard_normal(dims), A
 
 
 def gaussian(rng: np.random.Generator, dims) -> np.ndarray:
@@ -189,6 +232,57 @@ def tucker_lowrank_torch(k: int, dims, core_dims, noise_rel: float, decay=None,
     if out_dtype is not None:
         X = X.to(out_dtype)
     return X, G, Us
+
+
+def cp_paper_torch(k: int, I: int, delta: float = 1e-4, device="cuda", out_dtype=None):
+    """``cp_paper`` at full size on the device: terms drawn with numpy (rng_for(k)),
+    assembled and noised (torch generator seeded SEED_BASE + k) in float64 on ``device``.
+    Returns (A_hat, A) as ``out_dtype`` / float64."""
+    import torch
+    rng = rng_for(k)
+    R = max(1, int(round(0.2 * I)))
+    dims = (I, I, 100 * I)
+    lam, (a, b, c) = _cp_terms(rng, dims, R)
+    at, bt, ct = (torch.from_numpy(x).to(device) for x in (a * lam, b, c))
+    A = torch.einsum("ir,jr,kr->ijk", at, bt, ct).contiguous()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + k)
+    Ah = A + delta * torch.randn(dims, generator=gen, device=device, dtype=torch.float64)
+    if out_dtype is not None:
+        Ah = Ah.to(out_dtype)
+    return Ah, A
+
+
+def tucker_paper_torch(k: int, I: int, delta: float = 1e-4, device="cuda", out_dtype=None):
+    """``tucker_paper`` at full size on the device; the noise-free tensor is returned in
+    ``out_dtype`` too (float64 would double the memory at I = 5000).
+    Returns (A_hat, A, core, factors)."""
+    import torch
+    rng = rng_for(k)
+    core = (max(1, int(round(0.01 * I))), 10, 10, 10)
+    dims = (I, 100, 100, 100)
+    G = rng.uniform(5.0, 10.0, size=core)
+    Us = [orthonormal(rng, d, r) for d, r in zip(dims, core)]
+    X = torch.from_numpy(G).to(device)
+    for n in range(1, 4):
+        Ut = torch.from_numpy(Us[n]).to(device)
+        X = torch.movedim(torch.tensordot(Ut, X, dims=([1], [n])), 0, n).contiguous()
+    # the largest mode last, in slabs, so float64 never holds the whole tensor twice
+    odt = out_dtype if out_dtype is not None else torch.float64
+    A = torch.empty(dims, dtype=odt, device=device)
+    Ah = torch.empty(dims, dtype=odt, device=device)
+    U0 = torch.from_numpy(Us[0]).to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + k)
+    Xf = X.reshape(core[0], -1)
+    for s in range(0, I, 256):
+        e = min(I, s + 256)
+        slab = (U0[s:e] @ Xf).reshape((e - s,) + dims[1:])
+        A[s:e] = slab.to(odt)
+        Ah[s:e] = (slab + delta * torch.randn(slab.shape, generator=gen, device=device,
+                                              dtype=torch.float64)).to(odt)
+        del slab
+    return Ah, A, G, Us
 
 
 def workload_4way_torch(dims=(200, 200, 200, 200), R=20, noise_rel=1e-4, device="cuda"):
