@@ -447,7 +447,7 @@ __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
     if (tid == 0) {
       double e = 0.0;
       for (int w = 0; w < NW; ++w) e += red[w];
-      a.res2[0] = a.rsum ? a.rsum[0] : (a.norm2 - e);
+      a.res2[0] = a.rsum ? a.rsum[0] : ((a.norm2p ? a.norm2p[0] : a.norm2) - e);
       a.res2[1] = e;
     }
     // L_{k+1} = L_acc G_V^{-1}, with the Gram of L_{k+1} for PREP

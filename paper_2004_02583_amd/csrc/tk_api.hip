@@ -89,9 +89,11 @@ bool valid_dtype(int dt) { return dt == TK_F64 || dt == TK_F32 || dt == TK_BF16;
 // Device status block read back once per sweep.
 struct DevStatus {
   int status;
-  int prep_status;   // failure of the speculative preparation of the next sweep
-  double res2;
-  double energy;
+  // failure of the speculative preparation made by sweep k, in slot k & 1
+  int prep_status[2];
+  int pad;
+  // sweep k, slot k & 1: [0] = res^2, [1] = tr(Gq^{-1} G_V)
+  double res[2][2];
   double norm2;
   double rsum;
 };
@@ -256,16 +258,19 @@ void init_finish_enqueue(const View& v, int R, int xdt, int resid_mode, ModeWs& 
   a.m = v.I; a.r = R; a.ops = STEP_QR | STEP_PREP;
   a.Qin = w.Lacc; a.Q1 = w.Q1; a.Qout = w.L;
   a.Lq = w.Lq; a.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; a.Wq = w.Wq;
-  a.status = &w.st->status; a.prep_status = &w.st->prep_status;
+  a.status = &w.st->status; a.prep_status = &w.st->prep_status[0];
   launch_mode_step(a, cdtype(xdt), s);
 }
 
 // One sweep of Algorithm 3.3 from w.L, whose L~ (w.Lq), inverse Gram factor (w.Wq)
 // and compute-type copy (w.Lr, explicit residual) are already prepared:
 // R-update (never stored when fused), L-update into w.Lnext, residual into
-// st->res2, and the speculative preparation of the sweep from w.Lnext.
+// st->res[slot], and the speculative preparation of the sweep from w.Lnext
+// (its failure into st->prep_status[slot]).  ||X||^2 is norm2, or *norm2p on
+// the device when norm2p is non-null.
 void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
-                   int resid_mode, ModeWs& w, hipStream_t s) {
+                   int resid_mode, ModeWs& w, hipStream_t s, int slot = 0,
+                   const double* norm2p = nullptr) {
   const int64_t IR = v.I * (int64_t)R;
   const int cdt = cdtype(xdt);
   const bool expl = resid_mode == TK_RESID_EXPLICIT;
@@ -306,14 +311,14 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
   }
   StepArgs a{};
   a.m = v.I; a.r = R; a.ops = STEP_SOLVE | STEP_PREP | STEP_PREP_SPECULATIVE;
-  a.Lacc = w.Lacc; a.GV = w.GV; a.Lnext = w.Lnext; a.norm2 = norm2;
+  a.Lacc = w.Lacc; a.GV = w.GV; a.Lnext = w.Lnext; a.norm2 = norm2; a.norm2p = norm2p;
   if (expl) {
     launch_reduce_parts<double>(w.sparts, nres, 1, 1, &w.st->rsum, w.rtmp, s);
     a.rsum = &w.st->rsum;
   }
-  a.res2 = &w.st->res2;
+  a.res2 = w.st->res[slot];
   a.Lq = w.Lq; a.Lr = expl ? w.Lr : nullptr; a.Wq = w.Wq;
-  a.status = &w.st->status; a.prep_status = &w.st->prep_status;
+  a.status = &w.st->status; a.prep_status = &w.st->prep_status[slot];
   launch_mode_step(a, cdt, s);
 }
 
@@ -350,29 +355,58 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
     init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, want_norm ? &w.st->norm2 : nullptr, s);
   }
   init_finish_enqueue(v, R, xdt, o.resid_mode, w, s);
-  int rc = read_status(w.st, &h, s);
-  if (rc) return rc;
-  if (want_norm) {
-    normx2 = h.norm2;
-    if (!isfinite(normx2)) return TK_ERR_NONFINITE;
+  // The stop test first runs after sweep 1, so with max_iters >= 1 the initial
+  // step and sweeps 0 and 1 are enqueued back to back and checked by one
+  // status read: ||X||^2 reaches the sweeps on the device, sweep 0 keeps its
+  // residual and its preparation status in slot 0, and every failure flag is
+  // sticky (kernels after a failed step run on stale but in-range data and
+  // their results are discarded with the error).
+  const bool defer = o.max_iters >= 1;
+  const double* n2p = want_norm ? &w.st->norm2 : nullptr;
+  bool have_norm = !want_norm;
+  int rc = TK_OK;
+  auto take_status = [&]() -> int {
+    int r2 = read_status(w.st, &h, s);
+    if (r2) return r2;
+    if (!have_norm) {
+      normx2 = h.norm2;
+      if (!isfinite(normx2)) return TK_ERR_NONFINITE;
+      have_norm = true;
+    }
+    return h.status;
+  };
+  if (!defer) {
+    rc = take_status();
+    if (rc) return rc;
   }
-  if (h.status) return h.status;
-  const double nA = norm_a >= 0.0 ? norm_a : sqrt(normx2);
+  double nA = 0.0;
   double res_prev = 0.0;
   for (int k = 0;; ++k) {
-    sweep_enqueue(X, xdt, v, R, normx2, o.resid_mode, w, s);
+    sweep_enqueue(X, xdt, v, R, normx2, o.resid_mode, w, s, k & 1, n2p);
     mr.sweeps++;
-    rc = read_status(w.st, &h, s);
+    if (defer && k == 0) {
+      // sweep 1 starts from L_1, prepared speculatively by sweep 0
+      std::swap(w.L, w.Lnext);
+      continue;
+    }
+    rc = take_status();
     if (rc) return rc;
-    if (h.status) return h.status;
-    double res = sqrt(h.res2 > 0.0 ? h.res2 : 0.0);
+    nA = norm_a >= 0.0 ? norm_a : sqrt(normx2);
+    if (defer && k == 1) {
+      if (h.prep_status[0]) return h.prep_status[0];
+      const double r0 = h.res[0][0];
+      res_prev = sqrt(r0 > 0.0 ? r0 : 0.0);
+      if (!isfinite(res_prev)) return TK_ERR_NONFINITE;
+    }
+    const double r2 = h.res[k & 1][0];
+    double res = sqrt(r2 > 0.0 ? r2 : 0.0);
     if (!isfinite(res)) return TK_ERR_NONFINITE;
     mr.resid = res;
     mr.iters = k;
     if (k >= 1 && fabs(res_prev - res) <= o.tol * nA) { mr.converged = 1; break; }
     if (k >= o.max_iters) { mr.converged = 0; break; }
     // the next sweep starts from L_{k+1}, whose preparation ran speculatively
-    if (h.prep_status) return h.prep_status;
+    if (h.prep_status[k & 1]) return h.prep_status[k & 1];
     std::swap(w.L, w.Lnext);
     res_prev = res;
   }
@@ -993,7 +1027,7 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
     p.m = v.I; p.r = R; p.ops = STEP_PREP;
     p.Qin = w.L;
     p.Lq = w.Lq; p.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; p.Wq = w.Wq;
-    p.status = &w.st->status; p.prep_status = &w.st->prep_status;
+    p.status = &w.st->status; p.prep_status = &w.st->prep_status[0];
     launch_mode_step(p, cdtype(a_dtype), s);
   }
   sweep_enqueue(A, a_dtype, v, R, norm2, resid_mode, w, s);
@@ -1001,7 +1035,7 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
   DevStatus h{};
   int rc = read_status(w.st, &h, s);
   if (rc) return rc;
-  *res2 = h.res2;
+  *res2 = h.res[0][0];
   return h.status;
 }
 

@@ -131,6 +131,7 @@ struct StepArgs {
   // res2[1] = tr(Gq^-1 GV) with Gq^-1 = Wq^T Wq (Wq as left by the last PREP)
   const double* Lacc; const double* GV; double* Lnext;
   double norm2; const double* rsum; double* res2;
+  const double* norm2p;  // when non-null, replaces norm2 (read on the device)
   // QR: Qout = Q of the reduced QR of Qin (Q1: m x r scratch)
   const double* Qin; double* Q1; double* Qout;
   // PREP from Lnext (SOLVE) or Qout (QR): Lq = L (L^T L)^{-1} in the compute
