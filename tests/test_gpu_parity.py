@@ -252,6 +252,28 @@ def test_rank_deficient_status(gpu_lib):
     assert e.value.code == -4
 
 
+@pytest.mark.parametrize("resid", ["trace", "explicit"])
+@pytest.mark.parametrize("max_iters", [0, 1, 2])
+def test_small_max_iters_parity(gpu_lib, max_iters, resid):
+    """Every status-read arrangement of a mode solve: with max_iters = 0 a read follows the
+    initial step; otherwise the initial step and sweeps 0 and 1 share one read, and later sweeps
+    have their own.  FP64 against the oracle: iteration counts, residuals and subspaces."""
+    tk = gpu_lib
+    rng = np.random.default_rng(23)
+    ranks = (6, 5, 4)
+    A = synth.tucker_lowrank(rng, (30, 26, 22), ranks, 0.3)[0]
+    G, Us, info = tk.als_thosvd(to_gpu(A, "f64"), ranks, tol=1e-15, max_iters=max_iters,
+                                seed=3, resid_mode=resid)
+    ref = o.thosvd_als(A, ranks, tol=1e-15, max_iters=max_iters, seed=3)
+    assert info["status"] == "TK_NOT_CONVERGED"
+    for n in range(3):
+        assert info["iters"][n] == ref.info[n].iters == max_iters
+        assert not info["converged"][n]
+        assert abs(info["resid"][n] - ref.info[n].resid) <= 1e-9 * ref.norm_a
+        assert np.max(o.principal_angles(np64(Us[n]), ref.U[n])) < 1e-8
+    assert abs(info["norm_a"] - ref.norm_a) <= 1e-12 * ref.norm_a
+
+
 def test_not_converged_status(gpu_lib):
     tk = gpu_lib
     rng = np.random.default_rng(31)
