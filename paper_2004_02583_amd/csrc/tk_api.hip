@@ -329,14 +329,19 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
 // entry the initial pass computes it and returns it there.  On return U64
 // (FP64 I x R) holds Q of the reduced QR of the returned L.  With L0 (FP64
 // I x R, device; may alias U64) the iteration starts from L0 instead of the
-// sketch (a warm start), and ||X||^2 comes from a pass of its own.
+// sketch (a warm start), and ||X||^2 comes from a pass of its own.  With
+// defer_qr, w.st is the caller's status block for the whole call: its
+// failure flag is kept from earlier modes (and checked by every read), and
+// the final QR's failure is left there for the caller's next read instead of
+// being read back here.
 int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, double& normx2,
                double norm_a, int mode, ModeWs& w, double* U64, ModeResult& mr,
-               hipStream_t s, const double* L0 = nullptr) {
+               hipStream_t s, const double* L0 = nullptr, bool defer_qr = false) {
   mr.iters = 0; mr.converged = 1; mr.sweeps = 0; mr.resid = 0.0;
   DevStatus h{};
   const bool want_norm = normx2 < 0.0;
-  HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
+  if (defer_qr) HIPCHK(hipMemsetAsync(w.st->prep_status, 0, sizeof(w.st->prep_status), s));
+  else HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
   if (R == v.I) {
     if (want_norm) {
       norm2_enqueue(X, xdt, v.P * v.I * v.Q, w.sparts, &w.st->norm2, w.rtmp, s);
@@ -411,6 +416,7 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
     res_prev = res;
   }
   qr_enqueue(w.L, v.I, R, U64, w.Q1, &w.st->status, s);
+  if (defer_qr) return TK_OK;
   rc = read_status(w.st, &h, s);
   if (rc) return rc;
   return h.status;
@@ -542,7 +548,11 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   void* bufB = ar.take(ech * cs);
   double* U64[TK_MAX_ORDER];
   for (int n = 0; n < N; ++n) U64[n] = (double*)ar.take((size_t)dims[n] * ranks[n] * 8);
+  // one status block for the whole call: a mode's final QR reports a failure
+  // through the next read (the next mode's, or the one at the end)
+  DevStatus* cst = (DevStatus*)ar.take(sizeof(DevStatus));
   Arena mar(ar.base + ar.off, ar.cap - ar.off);
+  HIPCHK(hipMemsetAsync(cst, 0, sizeof(DevStatus), s));
 
   // ||A||^2 (E5.01 uses the input's norm for every mode) comes out of the
   // first mode's initial pass over A; in st-HOSVD each later mode's initial
@@ -560,10 +570,11 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
     Arena tmp = mar;
     ModeWs w;
     carve_mode(tmp, which == 1 ? bdt : adt, v, R, w);
+    w.st = cst;
     ModeResult mr;
     double normb2 = (which == 1 && t > 0) ? -1.0 : norm2;
     rc = mode_solve(which == 1 ? B : A, which == 1 ? bdt : adt, v, R, o, normb2,
-                    norm2 >= 0.0 ? sqrt(norm2) : -1.0, n, w, U64[n], mr, s);
+                    norm2 >= 0.0 ? sqrt(norm2) : -1.0, n, w, U64[n], mr, s, nullptr, true);
     if (rc == TK_OK && norm2 < 0.0) {
       norm2 = normb2;
       if (info) info->norm_a = sqrt(norm2);
@@ -613,8 +624,15 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
       bdt = cdt;
     }
   }
-  HIPCHK(hipStreamSynchronize(s));
+  // the last mode's QR status (the read also waits for the whole stream)
+  DevStatus h{};
+  rc = read_status(cst, &h, s);
+  if (rc) return rc;
   HIPCHK(hipGetLastError());
+  if (h.status) {
+    if (info) info->status = h.status;
+    return h.status;
+  }
   if (info) info->status = worst;
   return worst;
 }
