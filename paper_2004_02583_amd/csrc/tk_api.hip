@@ -424,8 +424,8 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
 
 // Singular vectors of X_(mode) inside the span of the orthonormal Q (FP64 I x R;
 // Section 3, after Algorithm 3.4): M = Q^T X_(mode) X_(mode)^T Q from one streaming
-// pass with Q (in the compute dtype) as L~, its eigenvectors W (FP64 Jacobi) into w.CL,
-// and Q W into w.Lnext.
+// pass with Q (in the compute dtype) as L~, its eigenvectors W (FP64 Jacobi) into w.CL
+// (the eigenvalues into w.Wq, unused afterwards), and Q W into w.Lnext.
 int svec_enqueue(const void* X, int xdt, const View& v, int R, const double* Q, ModeWs& w,
                  hipStream_t s) {
   const int64_t IR = v.I * (int64_t)R;

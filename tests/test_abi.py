@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2004_02583_amd import _lib as L
@@ -164,13 +166,13 @@ def test_st_order_auto_host(lib):
     """The automatic st-HOSVD order is host logic: it runs without a GPU and equals the
     oracle's exhaustive eq. 2.2 minimiser (integers, compared exactly)."""
     from oracle import tucker_oracle as o
-    rng = __import__("numpy").random.default_rng(60)
+    rng = np.random.default_rng(60)
     for N in (1, 2, 3, 4, 5, 6):
         for _ in range(6):
             dims = [int(x) for x in rng.integers(2, 200, N)]
             while True:
                 ranks = [int(rng.integers(1, min(d, 64) + 1)) for d in dims]
-                others_ok = all(N == 1 or ranks[n] <= int(__import__("numpy").prod(
+                others_ok = all(N == 1 or ranks[n] <= int(np.prod(
                     [ranks[k] for k in range(N) if k != n])) for n in range(N))
                 if others_ok:
                     break
