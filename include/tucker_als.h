@@ -288,7 +288,10 @@ TK_API size_t als_sthosvd_batched_workspace_bytes(int32_t count, const int64_t* 
  * After the last mode G = Y x_{N-1} U_{N-1}^T and the error
  * e = sqrt(||A||^2 - ||G||^2) / ||A|| (orthonormal factors); the iteration
  * stops when |e_prev - e| <= tol, e_prev starting at the error of the given
- * factors.
+ * factors.  With FP32/BF16 storage ||G||^2 comes from the FP32 core, whose
+ * rounding leaves an absolute error of a few 1e-9 on e^2: e is meaningful
+ * down to about 3e-4, and below that tol should not be relied on (use
+ * max_iters, and measure the error by reconstruction).
  *  A      device, input tensor (dtype a_dtype), as for als_thosvd.
  *  U      host array of N device pointers, in/out: I_n x R_n row-major with
  *         orthonormal columns on entry (FP64 when a_dtype == TK_F64, else

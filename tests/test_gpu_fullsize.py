@@ -145,3 +145,70 @@ def test_fullsize_sthosvd_bf16_storage(gpu_lib, big):
     e, _ = _relerr_and_core_norm(tk, A, G, Us)
     assert e <= 1e-4 + 1e-2, e
     assert e <= 1.2e-4, e   # observed ~1.02e-4: BF16 rounding falls outside the subspace
+
+
+def _mode_matrix(A, n):
+    """A_(n) in FP64 on the device (plain PyTorch), I_n x prod of the other dims."""
+    return A.movedim(n, 0).reshape(A.shape[n], -1).double()
+
+
+def test_fullsize_thosvd_singular_vectors(gpu_lib, big):
+    """Singular vectors at full size (Section 3, after Algorithm 3.4): each U_n diagonalises
+    U_n^T A_(n) A_(n)^T U_n (FP64, plain PyTorch) in descending order, to the FP32 rounding of
+    the Gram the device forms (2^-22 lambda_1), and the error equals the QR basis's."""
+    tk = gpu_lib
+    A = big["A"]
+    flush("fullsize t-HOSVD-ALS FP32 with singular vectors")
+    G, Us, info = tk.als_thosvd(A, (R,) * 4, tol=1e-4, singular_vectors=True)
+    assert info["status"] == "TK_OK"
+    e_sv, nA = _relerr_and_core_norm(tk, A, G, Us)
+    G0, U0, _ = tk.als_thosvd(A, (R,) * 4, tol=1e-4)
+    e_qr, _ = _relerr_and_core_norm(tk, A, G0, U0)
+    assert abs(e_sv - e_qr) <= 1e-4 * e_qr, (e_sv, e_qr)
+    del G0, U0
+    for n in range(4):
+        U = Us[n].double()
+        np.testing.assert_allclose((U.T @ U).cpu().numpy(), np.eye(R), atol=1e-5)
+        X = _mode_matrix(A, n)
+        C = U.T @ X
+        del X
+        M = (C @ C.T).cpu().numpy()
+        del C
+        lam = np.diag(M)
+        off = M - np.diag(lam)
+        flush(f"  mode {n}: max off-diagonal / lambda_1 {np.abs(off).max() / lam[0]:.2e}")
+        assert np.abs(off).max() <= 2.0 ** -20 * lam[0]
+        assert np.all(np.diff(lam) <= 2.0 ** -20 * lam[0])
+
+
+def test_fullsize_hooi_from_thosvd(gpu_lib, big):
+    """Three HOOI iterations from the t-HOSVD-ALS factors at full size.  The reconstruction
+    error does not rise and stays above every single-mode Eckart-Young error (trailing
+    eigenvalues of the FP64 mode Grams, plain PyTorch).  The device's own error comes from
+    e^2 = 1 - ||G||^2 / ||A||^2 with the FP32 core, whose rounding puts an absolute error of a
+    few 1e-9 on e^2 (measured 1.5e-9 and 3.8e-9 here, where e^2 = 1e-8): it is checked against
+    the reconstruction to 1e-8 in e^2, i.e. it means little below e ~ 3e-4."""
+    tk = gpu_lib
+    A = big["A"]
+    flush("fullsize HOOI from t-HOSVD-ALS")
+    G0, U0, _ = tk.als_thosvd(A, (R,) * 4, tol=1e-4)
+    e0, nA = _relerr_and_core_norm(tk, A, G0, U0)
+    del G0
+    G, Us, info = tk.hooi(A, U0, tol=0.0, max_iters=3, als_max_iters=2)
+    assert info["status"] in ("TK_OK", "TK_NOT_CONVERGED") and info["iters"] == 3
+    e, _ = _relerr_and_core_norm(tk, A, G, Us)
+    flush(f"  reconstruction error {e0:.7e} -> {e:.7e}; device's own "
+          f"{info['relerr_init']:.6e} -> {info['relerr']:.6e}")
+    assert e <= e0 * (1 + 1e-5)
+    assert abs(info["relerr"] ** 2 - e ** 2) <= 1e-8
+    assert abs(info["relerr_init"] ** 2 - e0 ** 2) <= 1e-8
+    for U in Us:
+        Uh = U.double().cpu().numpy()
+        np.testing.assert_allclose(Uh.T @ Uh, np.eye(R), atol=1e-5)
+    nA2 = nA * nA
+    for n in range(4):
+        X = _mode_matrix(A, n)
+        w = torch.linalg.eigvalsh(X @ X.T)
+        del X
+        gam = max(nA2 - float(w[-R:].sum()), 0.0)
+        assert gam ** 0.5 <= e * nA * (1 + 1e-4), (n, gam ** 0.5, e * nA)
