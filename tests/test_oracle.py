@@ -549,3 +549,99 @@ def test_loss_gradient_symmetry():
     for U, dU in zip(Us, dUs):
         M = U.T @ dU
         np.testing.assert_allclose(M, M.T, atol=1e-12)
+
+
+# ------------------------------------------- principal angles, tail energies
+
+def _planes_at_angles(rng, n, thetas):
+    """Two k-dimensional subspaces of R^n whose principal angles are exactly
+    ``thetas`` (by construction: the j-th basis vectors of the two spaces span
+    a plane of their own, orthogonal to every other pair's), then turned by a
+    random rotation of R^n and given non-orthonormal bases."""
+    k = len(thetas)
+    assert n >= 2 * k
+    X = np.zeros((n, k))
+    Y = np.zeros((n, k))
+    for j, t in enumerate(thetas):
+        X[2 * j, j] = 1.0
+        Y[2 * j, j] = np.cos(t)
+        Y[2 * j + 1, j] = np.sin(t)
+    Qr, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Mx = rng.standard_normal((k, k)) + 3.0 * np.eye(k)
+    My = rng.standard_normal((k, k)) + 3.0 * np.eye(k)
+    return Qr @ X @ Mx, Qr @ Y @ My
+
+
+def test_principal_angles_constructed():
+    """Principal angles (used by Theorem 2's subspace statement) against
+    subspaces built at known angles: one of 1e-9 rad (the sine branch), one
+    of 1.2 rad (the cosine branch), and 0.35 rad in between."""
+    rng = np.random.default_rng(11)
+    thetas = np.array([1e-9, 0.35, 1.2])
+    U1, U2 = _planes_at_angles(rng, 8, thetas)
+    got = np.sort(o.principal_angles(U1, U2))
+    # the rotation and the mixing matrices cost a few ulps of the sines
+    assert abs(got[0] - 1e-9) <= 2e-15, got[0]
+    np.testing.assert_allclose(got[1:], thetas[1:], rtol=0, atol=1e-14)
+    # symmetric in its arguments
+    np.testing.assert_allclose(np.sort(o.principal_angles(U2, U1)), got, rtol=0, atol=2e-15)
+
+
+def test_principal_angles_extremes():
+    """Equal spans give zero angles; orthogonal spans give pi/2."""
+    rng = np.random.default_rng(12)
+    U, _ = np.linalg.qr(rng.standard_normal((9, 3)))
+    M = rng.standard_normal((3, 3)) + 3.0 * np.eye(3)
+    assert np.max(o.principal_angles(U, U @ M)) <= 1e-15
+    U1, U2 = _planes_at_angles(rng, 6, [np.pi / 2] * 3)
+    np.testing.assert_allclose(o.principal_angles(U1, U2), np.pi / 2, rtol=0, atol=1e-14)
+
+
+def test_subspace_distance_is_projector_gap():
+    """For equal-dimension subspaces, sin of the largest principal angle equals
+    the spectral norm of the difference of the orthogonal projectors, computed
+    here directly from the projectors."""
+    rng = np.random.default_rng(13)
+    for thetas in ([1e-7, 0.2], [0.4, 0.9, 1.5], [0.0, 0.0]):
+        U1, U2 = _planes_at_angles(rng, 7, thetas)
+        Q1, _ = np.linalg.qr(U1)
+        Q2, _ = np.linalg.qr(U2)
+        gap = np.linalg.norm(Q1 @ Q1.T - Q2 @ Q2.T, 2)
+        assert abs(o.subspace_distance(U1, U2) - gap) <= 1e-14
+        assert abs(o.subspace_distance(U1, U2) - np.sin(max(thetas))) <= 1e-14
+
+
+def test_tail_energies_closed_form():
+    """gamma_n of Lemma 2 (eq. E5.1) on a tensor with a diagonal core and
+    orthonormal factors: every unfolding has exactly the core's diagonal
+    entries as singular values (the Khatri-Rao columns of orthonormal factors
+    are orthonormal), so gamma_n is the sum of the squares of the diagonal
+    entries beyond the R_n largest."""
+    rng = np.random.default_rng(14)
+    lam = np.array([9.0, -7.0, 5.5, 4.0, 2.5, 1.0])
+    dims = (10, 8, 12)
+    Us = [np.linalg.qr(rng.standard_normal((d, len(lam))))[0] for d in dims]
+    G = np.zeros((len(lam),) * 3)
+    for r, v in enumerate(lam):
+        G[r, r, r] = v
+    A = o.tucker_to_tensor(G, Us)
+    sq = np.sort(lam ** 2)[::-1]
+    for ranks in ((2, 3, 1), (5, 1, 4), (6, 6, 6)):
+        want = [float(np.sum(sq[R:])) for R in ranks]
+        np.testing.assert_allclose(o.tail_energies(A, ranks), want, rtol=1e-12, atol=1e-12)
+
+
+def test_tail_energies_first_mode_of_sthosvd():
+    """The st-HOSVD discarded energy of the first processed mode is that
+    mode's gamma_n (Algorithm 3.2 starts from A itself), and every later mode's
+    discarded energy is at most its gamma_n (projection can only remove
+    energy)."""
+    rng = np.random.default_rng(15)
+    A = rng.standard_normal((7, 6, 5))
+    ranks = (3, 2, 4)
+    gam = o.tail_energies(A, ranks)
+    for order in ((0, 1, 2), (2, 0, 1), (1, 2, 0)):
+        _, disc = o.sthosvd_svd(A, ranks, order=order)
+        assert abs(disc[order[0]] - gam[order[0]]) <= 1e-12 * gam[order[0]]
+        for n in order[1:]:
+            assert disc[n] <= gam[n] * (1 + 1e-12)
