@@ -302,8 +302,10 @@ class TuckerResult:
 
 
 def _mode_factor(Bn: np.ndarray, R: int, seed: int, mode: int, tol: float,
-                 max_iters: int, norm_ref: float):
+                 max_iters: int, norm_ref: float, L0=None):
     """One mode of Algorithms 3.4/3.5: ALS on B_(n), then reduced QR of L.
+    ``L0`` is Algorithm 3.3's initial guess when given (a warm start); the
+    Section 5 sketch otherwise.
 
     Returns (U_n, R_hat, R_k, ModeInfo)."""
     In, J = Bn.shape
@@ -312,8 +314,9 @@ def _mode_factor(Bn: np.ndarray, R: int, seed: int, mode: int, tol: float,
         U = np.eye(In)
         resid = 0.0
         return U, np.eye(In), Bn.T.copy(), ModeInfo(0, True, [resid], resid)
-    S = init_sketch(seed, mode, J, R)
-    L0 = als_initial_guess(Bn, S)
+    if L0 is None:
+        S = init_sketch(seed, mode, J, R)
+        L0 = als_initial_guess(Bn, S)
     res = als(Bn, R, L0, tol, max_iters, norm_ref)
     Q, Rhat = qr_signfix(res.L)
     return Q, Rhat, res.R, ModeInfo(res.iters, res.converged, res.residuals,
@@ -334,17 +337,21 @@ def singular_vectors_from_basis(An: np.ndarray, Q: np.ndarray):
 
 
 def thosvd_als(A: np.ndarray, ranks, tol: float = 1e-4, max_iters: int = 50,
-               seed: int = 0, singular_vectors: bool = False) -> TuckerResult:
+               seed: int = 0, singular_vectors: bool = False,
+               init=None) -> TuckerResult:
     """Algorithm 3.4 (t-HOSVD-ALS): per mode, ALS on A_(n), U^(n) = Q of the
     reduced QR of L; then G = A x_1 U^(1)T ... x_N U^(N)T.  With
     ``singular_vectors`` the factor step is replaced by the singular vectors
-    of A_(n) within that basis (``singular_vectors_from_basis``)."""
+    of A_(n) within that basis (``singular_vectors_from_basis``).  ``init``:
+    None, or per mode an I_n x R_n initial guess L_0 of Algorithm 3.3 (or
+    None for the Section 5 sketch)."""
     A = np.asarray(A, dtype=np.float64)
     nA = frob(A)
     Us, infos = [], []
     for n in range(A.ndim):
+        L0 = None if init is None else init[n]
         U, _, _, info = _mode_factor(unfold(A, n), ranks[n], seed, n, tol,
-                                     max_iters, nA)
+                                     max_iters, nA, L0)
         if singular_vectors:
             U, _ = singular_vectors_from_basis(unfold(A, n), U)
         Us.append(U)
@@ -355,13 +362,15 @@ def thosvd_als(A: np.ndarray, ranks, tol: float = 1e-4, max_iters: int = 50,
 
 def sthosvd_als(A: np.ndarray, ranks, order=None, tol: float = 1e-4,
                 max_iters: int = 50, seed: int = 0,
-                check_identity: bool = True) -> TuckerResult:
+                check_identity: bool = True, init=None) -> TuckerResult:
     """Algorithm 3.5 (st-HOSVD-ALS) with the literal truncation
     B_(n) <- R_hat R^T.
 
     With ``check_identity`` the literal truncation is compared with the
     mode-n product B x_n U^(n)T; the two agree because R is the
     least-squares solution for the very L that was QR-factorised.
+    ``init`` as for ``thosvd_als`` (L_0 of mode n has I_n rows whatever the
+    truncation of the other modes).
     """
     A = np.asarray(A, dtype=np.float64)
     N = A.ndim
@@ -372,8 +381,9 @@ def sthosvd_als(A: np.ndarray, ranks, order=None, tol: float = 1e-4,
     infos = [None] * N
     for n in order:
         Bn = unfold(B, n)
+        L0 = None if init is None else init[n]
         U, Rhat, Rk, info = _mode_factor(Bn, ranks[n], seed, n, tol,
-                                         max_iters, nA)
+                                         max_iters, nA, L0)
         newshape = list(B.shape)
         newshape[n] = ranks[n]
         Bnew = fold(Rhat @ Rk.T, n, newshape)

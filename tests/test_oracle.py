@@ -325,6 +325,35 @@ def test_als_matches_svd_at_tight_tolerance():
     assert _rel(o.relerr(A, als_s.G, als_s.U), o.relerr(A, svd_s.G, svd_s.U)) < 1e-10
 
 
+def test_warm_start_from_dominant_subspace():
+    """Algorithm 3.3 takes L_0 as input (a warm start).  Started from any basis of
+    the dominant subspace (here the SVD's, mixed by a random invertible matrix),
+    res_0 is already the Eckart-Young residual of the unfolding, the stop test
+    fires at k = 1, and the result is the SVD-based t-/st-HOSVD."""
+    rng = np.random.default_rng(19)
+    A = synth.tucker_lowrank(rng, (14, 12, 16), (4, 3, 5), 0.05)[0]
+    ranks = (4, 3, 5)
+    svd_t = o.thosvd_svd(A, ranks)
+    init = [U @ rng.standard_normal((U.shape[1], U.shape[1])) for U in svd_t.U]
+    t = o.thosvd_als(A, ranks, tol=1e-10, init=init)
+    for n in range(3):
+        sv = np.linalg.svd(o.unfold(A, n), compute_uv=False)
+        tail = np.sqrt(np.sum(sv[ranks[n]:] ** 2))
+        assert t.info[n].iters == 1 and t.info[n].converged
+        assert abs(t.info[n].residuals[0] - tail) <= 1e-10 * o.frob(A)
+        assert np.max(o.principal_angles(t.U[n], svd_t.U[n])) < 1e-9
+    assert _rel(o.relerr(A, t.G, t.U), o.relerr(A, svd_t.G, svd_t.U)) < 1e-10
+    svd_s = o.sthosvd_svd(A, ranks, order=[2, 0, 1])[0]
+    s_ = o.sthosvd_als(A, ranks, order=[2, 0, 1], tol=1e-10, init=svd_s.U)
+    assert all(i.iters == 1 for i in s_.info)
+    assert _rel(o.relerr(A, s_.G, s_.U), o.relerr(A, svd_s.G, svd_s.U)) < 1e-10
+    # a None entry keeps the Section 5 sketch for that mode
+    part = o.thosvd_als(A, ranks, tol=1e-8, seed=4, init=[None, init[1], None])
+    full = o.thosvd_als(A, ranks, tol=1e-8, seed=4)
+    assert part.info[0].residuals == full.info[0].residuals
+    assert part.info[1].iters == 1
+
+
 def test_full_rank_mode_is_identity():
     rng = np.random.default_rng(18)
     A = rng.standard_normal((4, 9, 8))
