@@ -59,6 +59,8 @@ typedef enum {
 typedef enum {
   TK_OK = 0,
   TK_NOT_CONVERGED = 1,            /* results valid; some mode hit max_iters */
+  TK_SKIPPED = 2,                  /* per-mode report only: the mode was not
+                                      processed because an earlier one failed */
   TK_ERR_INVALID_ARG = -1,         /* null pointer, bad N/dims/ranks/order   */
   TK_ERR_UNSUPPORTED_DTYPE = -2,   /* dtype combination not provided         */
   TK_ERR_WORKSPACE_TOO_SMALL = -3, /* ws_bytes below the query's value       */
@@ -74,13 +76,30 @@ typedef enum {
  *   is the tensor being swept (A, or the truncated tensor of st-HOSVD), G_V =
  *   R^T R and G_L' is the Gram of the quantised L (L^T L)^{-1} the sweep
  *   actually used (no extra tensor work; ||B||^2 comes from the initial pass).
+ *   The subtraction cancels: with FP32 accumulation its absolute error is a
+ *   few 2^-24 ||B||^2 / sqrt(J / I_n) in res^2, which decides the stop test
+ *   when the residual is small and eta tight.
  * TK_RESID_EXPLICIT: res^2 = sum_j ||a_j - L v_j||^2 accumulated during the
  *   sweep from the fibres themselves (one more small contraction per fibre;
- *   no extra HBM traffic). */
+ *   no extra HBM traffic; free of that cancellation).
+ * TK_RESID_AUTO (default): per mode, TRACE for FP64 storage; for FP32 and BF16
+ *   storage EXPLICIT when the trace form cannot resolve the stop test at a
+ *   relative residual of 1e-4, i.e. when 4 * 2^-24 * sqrt((I_n + 64) / J)
+ *   exceeds 1e-4 * eta (J = prod_{k != n} of the swept tensor's dims), TRACE
+ *   otherwise (and when eta == 0).  tk_als_info.resid_form reports the choice. */
 typedef enum {
-  TK_RESID_TRACE = 0,
-  TK_RESID_EXPLICIT = 1
+  TK_RESID_AUTO = 0,
+  TK_RESID_TRACE = 1,
+  TK_RESID_EXPLICIT = 2
 } tk_resid_mode;
+
+/* Arithmetic of the tensor contractions.  Only TK_COMPUTE_AS_STORAGE exists:
+ * FP64 data contracts in FP64, FP32 and BF16 data on the matrix cores with
+ * FP32 accumulation (FP32 operands of BF16 products split exactly into BF16
+ * terms).  Other values are rejected with TK_ERR_UNSUPPORTED_DTYPE. */
+typedef enum {
+  TK_COMPUTE_AS_STORAGE = 0
+} tk_compute;
 
 /* Options of the ALS drivers.  Zero-initialise, set struct_size =
  * sizeof(tk_als_opts), then override fields; NULL opts means defaults. */
@@ -88,7 +107,7 @@ typedef struct {
   size_t struct_size;      /* sizeof(tk_als_opts)                           */
   double tol;              /* eta of eq. E5.01 (default 1e-4, Section 6)     */
   int32_t max_iters;       /* max L-updates per mode (default 50, Section 6) */
-  int32_t resid_mode;      /* tk_resid_mode (default TK_RESID_TRACE)          */
+  int32_t resid_mode;      /* tk_resid_mode (default TK_RESID_AUTO)           */
   uint64_t seed;           /* seed of the initial sketch S (Section 5)        */
   const int32_t* order;    /* host; st-HOSVD processing order, a permutation
                               of 0..N-1 (Algorithm 3.5); NULL = 0..N-1      */
@@ -96,6 +115,17 @@ typedef struct {
                               by the singular vectors of A_(n) within its
                               span (Section 3, after Algorithm 3.4); 0 keeps
                               the QR basis (default)                        */
+  int32_t compute;         /* tk_compute (default TK_COMPUTE_AS_STORAGE)      */
+  const void* const* init_U; /* host array of N device pointers or NULL: the
+                              initial guess L_0 of Algorithm 3.3 per mode
+                              (I_n x R_n row-major, full column rank, FP64
+                              when a_dtype == TK_F64 else FP32), used instead
+                              of the Section 5 sketch (a warm start); a NULL
+                              entry keeps the sketch for that mode.  Only its
+                              span matters: the iteration is started from
+                              the Q of its reduced QR.  With a warm start of
+                              the first processed mode ||A|| takes one pass
+                              of its own.                                   */
 } tk_als_opts;
 
 /* Per-call report. */
@@ -106,6 +136,12 @@ typedef struct {
   double norm_a;                   /* ||A||_F of the input                   */
   int32_t sweeps;                  /* tensor sweeps executed in total        */
   int32_t status;                  /* same as the return value               */
+  int32_t mode_status[TK_MAX_ORDER]; /* per mode: TK_OK, TK_NOT_CONVERGED, the
+                                      failure of that mode (negative; a final
+                                      QR's rank deficiency counts for its
+                                      mode), or TK_SKIPPED                    */
+  int32_t resid_form[TK_MAX_ORDER];  /* TK_RESID_TRACE or TK_RESID_EXPLICIT:
+                                      the form mode n's stop test used        */
 } tk_als_info;
 
 /* --------------------------------------------------------------------------
@@ -122,8 +158,10 @@ typedef struct {
  * final B.  R_n == I_n yields U_n = identity with no iterations.
  *
  *  A      device, input tensor, dtype a_dtype, dims[0..N-1] row-major.
- *  dims   host, int64[N].        ranks  host, int32[N], 1 <= R_n <= I_n and
- *                                       R_n <= prod_{k != n} R_k.
+ *  dims   host, int64[N].        ranks  host, int32[N], 1 <= R_n <= I_n,
+ *                                       R_n <= 64 (the r x r small linear
+ *                                       algebra runs in one workgroup's LDS)
+ *                                       and R_n <= prod_{k != n} R_k.
  *  opts   host or NULL.
  *  U      host array of N device pointers; U[n] receives I_n x R_n
  *         row-major, FP64 when a_dtype == TK_F64, else FP32.
@@ -192,7 +230,8 @@ TK_API size_t tucker_reconstruct_workspace_bytes(int32_t dtype, int32_t N,
  * FP64 when the inputs are FP64, else FP32.  This is the gradient of a
  * mode-n product with respect to its matrix: for Y = X x_n M,
  * dL/dM = (dL/dY)_(n) X_(n)^T (adjoint of the Section 2 definition).
- * Inputs (F64, F64) or (F32, F32).  ws >= contract_allbut_workspace_bytes.
+ * Inputs (F64, F64) or (F32, F32); 1 <= J <= 64 (TK_ERR_INVALID_ARG
+ * otherwise).  ws >= contract_allbut_workspace_bytes.
  * Asynchronous on `stream`. */
 TK_API int contract_allbut(const void* X, const void* Y, int32_t dtype, int32_t N,
                     const int64_t* xdims, int32_t mode, int64_t J, void* K,
@@ -208,18 +247,22 @@ TK_API size_t contract_allbut_workspace_bytes(int32_t dtype, int32_t N,
  * als_init_step: Section 5 initial guess on the mode-`mode` view of A.
  *   Y = A_(mode) S (I_mode x R, FP64 out, device) with S as in als_sthosvd,
  *   then L0 = Q of the reduced QR of Y (FP64, device, may alias nothing);
- *   *norm2 (host) receives ||A||_F^2.  ws >= als_workspace_bytes(1, ...)
- *   for a tensor of these dims with all ranks equal to R.
+ *   *norm2 (host) receives ||A||_F^2.  1 <= R <= min(I_mode, 64).
+ *   ws >= als_workspace_bytes(1, ...) for a tensor of these dims with all
+ *   ranks equal to R.
  *
  * als_sweep_step: one sweep of Algorithm 3.3 from L_k (FP64 I_mode x R,
  *   device): R_k = A_(mode)^T L_k (L_k^T L_k)^{-1} (never stored),
  *   L_{k+1} = A_(mode) R_k (R_k^T R_k)^{-1} written to L_next (FP64,
  *   device), *res2 (host) receives ||A_(mode) - L_k R_k^T||_F^2 computed as
- *   selected by resid_mode with norm2 = ||A||_F^2.
+ *   selected by resid_mode (TK_RESID_TRACE or TK_RESID_EXPLICIT; AUTO is
+ *   rejected here) with norm2 = ||A||_F^2.  1 <= R <= min(I_mode, 64).
  *
  * qr_f64: reduced QR of the FP64 m x r (row-major, device) matrix L into
- *   Q (m x r, device) with diag(R_hat) > 0 (CholeskyQR2 in FP64); Rhat
- *   (r x r, device) may be NULL.  Blocks until done.  Returns
+ *   Q (m x r, device) with diag(R_hat) > 0 (CholeskyQR2 in FP64),
+ *   1 <= r <= min(m, 64).  R_hat is not returned: Rhat is reserved and must
+ *   be NULL (TK_ERR_INVALID_ARG otherwise).  ws: device, at least
+ *   m*r*8 + 3*65536 bytes.  Blocks until done.  Returns
  *   TK_ERR_RANK_DEFICIENT when the Gram fails the pivot test. */
 TK_API int als_init_step(const void* A, int32_t a_dtype, int32_t N,
                   const int64_t* dims, int32_t mode, int32_t R, uint64_t seed,

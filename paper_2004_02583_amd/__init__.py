@@ -47,18 +47,31 @@ def _require_gpu(*ts):
             raise TuckerALSError(-1, "inputs must be contiguous")
 
 
-def _opts(tol, max_iters, seed, order, resid_mode, singular_vectors=False):
+_RESID = {"auto": L.TK_RESID_AUTO, "trace": L.TK_RESID_TRACE,
+          "explicit": L.TK_RESID_EXPLICIT}
+_RESID_NAME = {v: k for k, v in _RESID.items()}
+
+
+def _opts(tol, max_iters, seed, order, resid_mode, singular_vectors=False, init_ptrs=None):
     o = L.tk_als_opts()
     o.struct_size = ctypes.sizeof(L.tk_als_opts)
     o.tol = float(tol)
     o.max_iters = int(max_iters)
     o.seed = int(seed) & ((1 << 64) - 1)
-    o.resid_mode = {"trace": L.TK_RESID_TRACE, "explicit": L.TK_RESID_EXPLICIT}[resid_mode]
+    if resid_mode not in _RESID:
+        raise TuckerALSError(-1, f"resid_mode {resid_mode!r}")
+    o.resid_mode = _RESID[resid_mode]
     o.singular_vectors = 1 if singular_vectors else 0
-    keep = None
+    o.compute = L.TK_COMPUTE_AS_STORAGE
+    keep = []
     if order is not None:
-        keep = L.i32arr(order)
-        o.order = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+        arr = L.i32arr(order)
+        keep.append(arr)
+        o.order = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    if init_ptrs is not None:
+        arr = (ctypes.c_void_p * len(init_ptrs))(*init_ptrs)
+        keep.append(arr)
+        o.init_U = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
     return o, keep
 
 
@@ -70,11 +83,13 @@ def _info_dict(info: L.tk_als_info, N: int) -> dict:
         norm_a=info.norm_a,
         sweeps=info.sweeps,
         status=L.STATUS.get(info.status, info.status),
+        mode_status=[L.STATUS.get(info.mode_status[n], info.mode_status[n]) for n in range(N)],
+        resid_form=[_RESID_NAME.get(info.resid_form[n], info.resid_form[n]) for n in range(N)],
     )
 
 
 def _driver(which, A, ranks, tol, max_iters, seed, order, resid_mode, workspace,
-            singular_vectors=False):
+            singular_vectors=False, init=None):
     lib = L.lib()
     _require_gpu(A)
     N = A.dim()
@@ -93,13 +108,28 @@ def _driver(which, A, ranks, tol, max_iters, seed, order, resid_mode, workspace,
     ws = workspace
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    o, keep = _opts(tol, max_iters, seed, order, resid_mode, singular_vectors)
+    init_keep, init_ptrs = [], None
+    if init is not None:
+        if len(init) != N:
+            raise TuckerALSError(-1, "init: one entry (or None) per mode")
+        init_ptrs = []
+        for n, L0 in enumerate(init):
+            if L0 is None:
+                init_ptrs.append(None)
+                continue
+            _require_gpu(L0)
+            if tuple(L0.shape) != (A.shape[n], ranks[n]) or L0.dtype != fdt:
+                raise TuckerALSError(-1, f"init[{n}]: expected {fdt} of shape "
+                                         f"{(A.shape[n], ranks[n])}")
+            init_keep.append(L0)
+            init_ptrs.append(L0.data_ptr())
+    o, keep = _opts(tol, max_iters, seed, order, resid_mode, singular_vectors, init_ptrs)
     info = L.tk_als_info()
     fn = lib.als_sthosvd if which == 1 else lib.als_thosvd
     rc = fn(ctypes.c_void_p(A.data_ptr()), adt, N, dims, rk, ctypes.byref(o),
             L.ptrarr([u.data_ptr() for u in Us]), ctypes.c_void_p(G.data_ptr()),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(info), _stream(dev))
-    del keep
+    del keep, init_keep
     L.check(rc, "als_sthosvd" if which == 1 else "als_thosvd", allow=(0, 1))
     return G, Us, _info_dict(info, N)
 
@@ -115,26 +145,31 @@ def st_order(dims, ranks):
 
 
 def als_sthosvd(A, ranks, tol=1e-4, max_iters=50, seed=0, order=None,
-                resid_mode="trace", workspace=None):
+                resid_mode="auto", workspace=None, init=None):
     """st-HOSVD-ALS (Algorithm 3.5).  Returns (G, [U_n], info).  order: None (natural),
-    a permutation, or "auto" (``st_order``)."""
+    a permutation, or "auto" (``st_order``).  resid_mode: "auto", "trace" or "explicit"
+    (the residual form of the eq. E5.01 stop test).  init: None, or one I_n x R_n
+    initial guess L_0 (or None) per mode, in the factor dtype (a warm start of
+    Algorithm 3.3)."""
     if isinstance(order, str):
         if order != "auto":
             raise TuckerALSError(-1, "order must be None, a permutation or 'auto'")
         order = st_order(list(A.shape), list(ranks))
-    return _driver(1, A, list(ranks), tol, max_iters, seed, order, resid_mode, workspace)
+    return _driver(1, A, list(ranks), tol, max_iters, seed, order, resid_mode, workspace,
+                   init=init)
 
 
-def als_thosvd(A, ranks, tol=1e-4, max_iters=50, seed=0, resid_mode="trace",
-               workspace=None, singular_vectors=False):
+def als_thosvd(A, ranks, tol=1e-4, max_iters=50, seed=0, resid_mode="auto",
+               workspace=None, singular_vectors=False, init=None):
     """t-HOSVD-ALS (Algorithm 3.4).  Returns (G, [U_n], info).  With singular_vectors the
-    factors are the singular vectors of A_(n) inside the ALS subspaces (Section 3)."""
+    factors are the singular vectors of A_(n) inside the ALS subspaces (Section 3).
+    init as for ``als_sthosvd``."""
     return _driver(0, A, list(ranks), tol, max_iters, seed, None, resid_mode, workspace,
-                   singular_vectors)
+                   singular_vectors, init=init)
 
 
 def hooi(A, factors, tol=1e-10, max_iters=50, als_tol=1e-8, als_max_iters=50, seed=0,
-         resid_mode="trace", workspace=None):
+         resid_mode="auto", workspace=None):
     """HOOI refinement (Section 6.3) started from ``factors`` (orthonormal I_n x R_n
     tensors, left unchanged).  Returns (G, [U_n], info) with the refined factors;
     als_tol / als_max_iters drive the warm-started inner ALS."""
@@ -275,7 +310,7 @@ def als_sweep_step(A, mode, Lk, norm2, resid_mode="trace"):
     ws = _step_ws(A, mode, R)
     Ln = torch.empty_like(Lk)
     r2 = ctypes.c_double(0.0)
-    rm = {"trace": L.TK_RESID_TRACE, "explicit": L.TK_RESID_EXPLICIT}[resid_mode]
+    rm = _RESID[resid_mode]
     rc = lib.als_sweep_step(ctypes.c_void_p(A.data_ptr()), _dtcode(A), A.dim(),
                             L.i64arr(A.shape), mode, R, ctypes.c_void_p(Lk.data_ptr()),
                             ctypes.c_void_p(Ln.data_ptr()), float(norm2), rm, ctypes.byref(r2),
@@ -323,7 +358,7 @@ def qr_f64(Lm):
     return Q
 
 
-def batched_sthosvd(tensors, ranks_list, tol=1e-4, max_iters=50, seed=0):
+def batched_sthosvd(tensors, ranks_list, tol=1e-4, max_iters=50, seed=0, resid_mode="auto"):
     """st-HOSVD-ALS of many small order-3 FP32 tensors in one batched call.
 
     Returns a list of (G, [U1, U2, U3], iters) and the per-tensor statuses."""
@@ -356,7 +391,7 @@ def batched_sthosvd(tensors, ranks_list, tol=1e-4, max_iters=50, seed=0):
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     iters = (ctypes.c_int32 * (3 * count))()
     status = (ctypes.c_int32 * count)()
-    o, keep = _opts(tol, max_iters, seed, None, "trace")
+    o, keep = _opts(tol, max_iters, seed, None, resid_mode)
     rc = lib.als_sthosvd_batched(ctypes.c_void_p(A_packed.data_ptr()), L.TK_F32, count, d3, r3,
                                  L.i64arr(a_off), ctypes.byref(o),
                                  ctypes.c_void_p(U_packed.data_ptr()), L.i64arr(u_off),

@@ -13,11 +13,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtucker_als.so")
 
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
-TK_RESID_TRACE, TK_RESID_EXPLICIT = 0, 1
+TK_RESID_AUTO, TK_RESID_TRACE, TK_RESID_EXPLICIT = 0, 1, 2
+TK_COMPUTE_AS_STORAGE = 0
 TK_MAX_ORDER = 8
 
 STATUS = {
-    0: "TK_OK", 1: "TK_NOT_CONVERGED", -1: "TK_ERR_INVALID_ARG",
+    0: "TK_OK", 1: "TK_NOT_CONVERGED", 2: "TK_SKIPPED", -1: "TK_ERR_INVALID_ARG",
     -2: "TK_ERR_UNSUPPORTED_DTYPE", -3: "TK_ERR_WORKSPACE_TOO_SMALL",
     -4: "TK_ERR_RANK_DEFICIENT", -5: "TK_ERR_NONFINITE", -6: "TK_ERR_HIP",
 }
@@ -42,6 +43,8 @@ class tk_als_opts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("order", ctypes.POINTER(ctypes.c_int32)),
         ("singular_vectors", ctypes.c_int32),
+        ("compute", ctypes.c_int32),
+        ("init_U", ctypes.POINTER(ctypes.c_void_p)),
     ]
 
 
@@ -53,6 +56,8 @@ class tk_als_info(ctypes.Structure):
         ("norm_a", ctypes.c_double),
         ("sweeps", ctypes.c_int32),
         ("status", ctypes.c_int32),
+        ("mode_status", ctypes.c_int32 * TK_MAX_ORDER),
+        ("resid_form", ctypes.c_int32 * TK_MAX_ORDER),
     ]
 
 

@@ -137,7 +137,9 @@ __device__ bool blk_qr(const double* L, int m, int r, double* Q1, double* Q, dou
 
 // One pass over the fibres of the view [P, I, Q] of X (FP32) in tiles of TJ:
 //  kind 0 (sweep): V = X^T W (W = L~ in LDS, FP32), G_V += V^T V (FP64 in
-//                  registers of thread < r(r+1)/2), Lacc += X V;
+//                  registers of thread < r(r+1)/2), Lacc += X V; with Lr
+//                  (L in LDS, FP32) also returns sum_j ||x_j - L v_j||^2
+//                  (the explicit residual, FP64 sums of FP32 differences);
 //  kind 1 (init):  V = rows of the Section 5 sketch, Lacc += X V;
 //  kind 2 (TTM):   V = X^T W (W = U in LDS), written to Y[p][r][q];
 //                  returns sum V^2 (FP64) for the next mode's norm.
@@ -146,7 +148,8 @@ __device__ bool blk_qr(const double* L, int m, int r, double* Q1, double* Q, dou
 template <int NTH, int TJ>
 __device__ double blk_pass(int kind, const float* X, const View v, int r, const float* W,
                            double* Lacc, double* gv, float* Y, uint64_t seed, int mode,
-                           float* Xt, float* Vt, int64_t* fb, double* red) {
+                           float* Xt, float* Vt, int64_t* fb, double* red,
+                           const float* Lr = nullptr) {
   constexpr int XS = TJ + 1;
   const int I = (int)v.I;
   const int64_t J = v.J();
@@ -210,6 +213,16 @@ __device__ double blk_pass(int kind, const float* X, const View v, int r, const 
         }
       }
     } else {
+      if (kind == 0 && Lr) {
+        for (int e = threadIdx.x; e < I * TJ; e += NTH) {
+          const int i = e / TJ, jj = e % TJ;
+          if (j0 + jj < J) {
+            float d = Xt[i * XS + jj];
+            for (int c = 0; c < r; ++c) d -= Lr[i * BR_MAX + c] * Vt[jj * BR_MAX + c];
+            ssum += (double)d * (double)d;
+          }
+        }
+      }
       if (kind == 0) {
         for (int h = 0; h < 2; ++h) {
           if ((int)threadIdx.x + NTH * h < np) {
@@ -239,7 +252,7 @@ __device__ double blk_pass(int kind, const float* X, const View v, int r, const 
     }
   }
   __syncthreads();
-  return kind == 2 ? blk_sum<NTH>(ssum, red) : 0.0;
+  return (kind == 2 || (kind == 0 && Lr)) ? blk_sum<NTH>(ssum, red) : 0.0;
 }
 
 struct BatchDesc {
@@ -262,6 +275,7 @@ struct BatchArgs {
   int64_t slot_bytes, belems;
   double tol;
   int max_iters;
+  int resid_mode;
   uint64_t seed;
 };
 
@@ -271,6 +285,7 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
   __shared__ float Xt[BI_MAX * XS];
   __shared__ float Vt[TJ * BR_MAX];
   __shared__ float Wl[BI_MAX * BR_MAX];
+  __shared__ float Ll[BI_MAX * BR_MAX];   // L in FP32 for the explicit residual
   __shared__ double G1[GV_MAX], G2[GV_MAX], GV[GV_MAX];
   __shared__ double red[NTH];
   __shared__ int64_t fb[TJ];
@@ -313,6 +328,12 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
         for (int e = threadIdx.x; e < I * I; e += NTH) U[e] = (e / I == e % I) ? 1.0f : 0.0f;
         __syncthreads();
       } else {
+        // residual form of the stop test (TK_RESID_AUTO resolved by the same rule
+        // as the single-tensor drivers: explicit where the trace form's rounding
+        // could decide the test)
+        bool expl = a.resid_mode == TK_RESID_EXPLICIT;
+        if (a.resid_mode == TK_RESID_AUTO && a.tol > 0.0)
+          expl = 4.0 * 0x1p-24 * sqrt((double)(v.I + 64) / (double)v.J()) > 1e-4 * a.tol;
         // initial guess (Section 5): Y = B_(n) S, L0 = Q of its QR
         double dummy[2] = {0.0, 0.0};
         blk_pass<NTH, TJ>(1, B, v, r, nullptr, S.Lacc, dummy, nullptr, a.seed, n, Xt, Vt, fb,
@@ -324,8 +345,10 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
           blk_gram<NTH>(S.L, I, r, G1);
           if (blk_chol<NTH>(G1, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
           blk_rsolve<NTH>(S.L, I, r, G1, 1, S.Q1);
-          for (int e = threadIdx.x; e < I * r; e += NTH)
+          for (int e = threadIdx.x; e < I * r; e += NTH) {
             Wl[(e / r) * BR_MAX + e % r] = (float)S.Q1[e];
+            if (expl) Ll[(e / r) * BR_MAX + e % r] = (float)S.L[e];
+          }
           __syncthreads();
           for (int e = threadIdx.x; e < r * (r + 1) / 2; e += NTH) {
             int aa = 0, rem = e;
@@ -340,7 +363,8 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
           if (blk_chol<NTH>(G2, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
           // sweep: V = B_(n)^T L~ (tiles), G_V, Lacc = B_(n) V
           double gv[2] = {0.0, 0.0};
-          blk_pass<NTH, TJ>(0, B, v, r, Wl, S.Lacc, gv, nullptr, 0, 0, Xt, Vt, fb, red);
+          const double rsum = blk_pass<NTH, TJ>(0, B, v, r, Wl, S.Lacc, gv, nullptr, 0, 0, Xt,
+                                                Vt, fb, red, expl ? Ll : nullptr);
           {
             const int np = r * (r + 1) / 2;
             for (int h = 0; h < 2; ++h) {
@@ -369,7 +393,7 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
             }
           }
           e = blk_sum<NTH>(e, red);
-          const double res2 = normB2 - e;
+          const double res2 = expl ? rsum : normB2 - e;
           const double res = sqrt(res2 > 0.0 ? res2 : 0.0);
           it = k;
           bool stop = false;
@@ -429,7 +453,7 @@ void launch_batched(const BatchLaunch& L, int cfg, hipStream_t s) {
   a.A = L.A; a.desc = (const BatchDesc*)L.desc; a.count = L.count;
   a.U = L.U; a.G = L.G; a.status = L.status; a.iters = L.iters; a.queue = L.queue;
   a.scratch = L.scratch; a.slot_bytes = L.slot_bytes; a.belems = L.belems;
-  a.tol = L.tol; a.max_iters = L.max_iters; a.seed = L.seed;
+  a.tol = L.tol; a.max_iters = L.max_iters; a.seed = L.seed; a.resid_mode = L.resid_mode;
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, L.queue, 1, 0);
   const dim3 grid(L.nwg);
   switch (cfg) {

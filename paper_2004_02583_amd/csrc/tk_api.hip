@@ -91,7 +91,8 @@ struct DevStatus {
   int status;
   // failure of the speculative preparation made by sweep k, in slot k & 1
   int prep_status[2];
-  int pad;
+  // failure of a mode's final QR whose check is left to the next read
+  int qr_status;
   // sweep k, slot k & 1: [0] = res^2, [1] = tr(Gq^{-1} G_V)
   double res[2][2];
   double norm2;
@@ -138,26 +139,31 @@ struct Opts {
   uint64_t seed;
   const int32_t* order;
   int svec;
+  const void* const* init_U;
 };
 
 int read_opts(const tk_als_opts* o, int N, Opts& out) {
   out.tol = 1e-4;
   out.max_iters = 50;
-  out.resid_mode = TK_RESID_TRACE;
+  out.resid_mode = TK_RESID_AUTO;
   out.seed = 0;
   out.order = nullptr;
   out.svec = 0;
+  out.init_U = nullptr;
   if (!o) return TK_OK;
   if (o->struct_size < sizeof(tk_als_opts)) return TK_ERR_INVALID_ARG;
   if (!(o->tol >= 0.0) || o->max_iters < 0) return TK_ERR_INVALID_ARG;
-  if (o->resid_mode != TK_RESID_TRACE && o->resid_mode != TK_RESID_EXPLICIT)
+  if (o->resid_mode != TK_RESID_AUTO && o->resid_mode != TK_RESID_TRACE &&
+      o->resid_mode != TK_RESID_EXPLICIT)
     return TK_ERR_INVALID_ARG;
+  if (o->compute != TK_COMPUTE_AS_STORAGE) return TK_ERR_UNSUPPORTED_DTYPE;
   out.tol = o->tol;
   out.max_iters = o->max_iters;
   out.resid_mode = o->resid_mode;
   out.seed = o->seed;
   out.order = o->order;
   out.svec = o->singular_vectors != 0;
+  out.init_U = o->init_U;
   if (out.order) {
     bool seen[TK_MAX_ORDER] = {false};
     for (int k = 0; k < N; ++k) {
@@ -216,8 +222,25 @@ int norm2_enqueue(const void* X, int xdt, int64_t n, double* sparts, double* out
 
 struct ModeResult {
   int iters, converged, sweeps;
+  int form;             // residual form the stop test used
+  int qr_failed;        // a status read found an earlier mode's deferred QR failure
   double resid;
 };
+
+// The residual form of a mode solve, TK_RESID_AUTO resolved.  With FP32
+// accumulation the trace form's res^2 = ||B||^2 - tr(...) carries a rounding of
+// about 2^-24 sqrt((I + 64) / J) ||B||^2 (rounding of the I-term sums of V and of
+// the fibre sums, averaged over J fibres), so at a relative residual rho its
+// error on res is that over 2 rho ||B||.  The explicit form is chosen when this
+// error could exceed a quarter of eta ||A|| at rho = 1e-4 (taking ||B|| ~ ||A||);
+// it costs one more small product per fibre and no tensor traffic.  FP64
+// storage, and eta = 0 (no stop test), keep the trace form.
+int resolve_resid_form(int resid_mode, int xdt, const View& v, double tol) {
+  if (resid_mode != TK_RESID_AUTO) return resid_mode;
+  if (cdtype(xdt) == TK_F64 || !(tol > 0.0)) return TK_RESID_TRACE;
+  const double crit = 4.0 * 0x1p-24 * sqrt((double)(v.I + 64) / (double)v.J());
+  return crit > 1e-4 * tol ? TK_RESID_EXPLICIT : TK_RESID_TRACE;
+}
 
 // Y (FP64, I x R) = B_(n) S  (Section 5 initial sketch), partial-reduced;
 // with norm2 != null the same pass also yields ||B||_F^2.
@@ -327,25 +350,39 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
 // input tensor; norm_a < 0: the norm of X).  normx2 = ||X||_F^2 of the
 // tensor being swept (trace form of the residual); when it is negative on
 // entry the initial pass computes it and returns it there.  On return U64
-// (FP64 I x R) holds Q of the reduced QR of the returned L.  With L0 (FP64
-// I x R, device; may alias U64) the iteration starts from L0 instead of the
-// sketch (a warm start), and ||X||^2 comes from a pass of its own.  With
-// defer_qr, w.st is the caller's status block for the whole call: its
-// failure flag is kept from earlier modes (and checked by every read), and
-// the final QR's failure is left there for the caller's next read instead of
-// being read back here.
+// (FP64 I x R) holds Q of the reduced QR of the returned L.  With L0 (I x R,
+// device, FP64 or FP32 as l0_dt; may alias U64) the iteration starts from the Q
+// of L0's reduced QR instead of the sketch (a warm start: only the span of L_0
+// matters to Algorithm 3.3), and ||X||^2 comes from a pass of its own.  With
+// defer_qr, w.st is the caller's status block for the whole call: its failure
+// flags are kept from earlier modes (and checked by every read), and the final
+// QR's failure is left in qr_status for the caller's next read instead of being
+// read back here; a read that finds an earlier mode's QR failure returns it
+// with mr.qr_failed set.
 int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, double& normx2,
                double norm_a, int mode, ModeWs& w, double* U64, ModeResult& mr,
-               hipStream_t s, const double* L0 = nullptr, bool defer_qr = false) {
-  mr.iters = 0; mr.converged = 1; mr.sweeps = 0; mr.resid = 0.0;
+               hipStream_t s, const void* L0 = nullptr, int l0_dt = TK_F64,
+               bool defer_qr = false) {
+  mr.iters = 0; mr.converged = 1; mr.sweeps = 0; mr.resid = 0.0; mr.qr_failed = 0;
+  const int form = resolve_resid_form(o.resid_mode, xdt, v, o.tol);
+  mr.form = form;
   DevStatus h{};
   const bool want_norm = normx2 < 0.0;
   if (defer_qr) HIPCHK(hipMemsetAsync(w.st->prep_status, 0, sizeof(w.st->prep_status), s));
   else HIPCHK(hipMemsetAsync(w.st, 0, sizeof(DevStatus), s));
+  auto read = [&]() -> int {
+    int r2 = read_status(w.st, &h, s);
+    if (r2) return r2;
+    if (h.qr_status) {
+      mr.qr_failed = 1;
+      return h.qr_status;
+    }
+    return TK_OK;
+  };
   if (R == v.I) {
     if (want_norm) {
       norm2_enqueue(X, xdt, v.P * v.I * v.Q, w.sparts, &w.st->norm2, w.rtmp, s);
-      int rc = read_status(w.st, &h, s);
+      int rc = read();
       if (rc) return rc;
       normx2 = h.norm2;
       if (!isfinite(normx2)) return TK_ERR_NONFINITE;
@@ -355,11 +392,14 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
   }
   if (L0) {
     if (want_norm) norm2_enqueue(X, xdt, v.P * v.I * v.Q, w.sparts, &w.st->norm2, w.rtmp, s);
-    HIPCHK(hipMemcpyAsync(w.Lacc, L0, (size_t)v.I * R * 8, hipMemcpyDeviceToDevice, s));
+    if (l0_dt == TK_F64)
+      HIPCHK(hipMemcpyAsync(w.Lacc, L0, (size_t)v.I * R * 8, hipMemcpyDeviceToDevice, s));
+    else
+      launch_widen<float>((const float*)L0, v.I * (int64_t)R, w.Lacc, s);
   } else {
     init_enqueue(X, xdt, v, R, o.seed, mode, w, w.Lacc, want_norm ? &w.st->norm2 : nullptr, s);
   }
-  init_finish_enqueue(v, R, xdt, o.resid_mode, w, s);
+  init_finish_enqueue(v, R, xdt, form, w, s);
   // The stop test first runs after sweep 1, so with max_iters >= 1 the initial
   // step and sweeps 0 and 1 are enqueued back to back and checked by one
   // status read: ||X||^2 reaches the sweeps on the device, sweep 0 keeps its
@@ -371,7 +411,7 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
   bool have_norm = !want_norm;
   int rc = TK_OK;
   auto take_status = [&]() -> int {
-    int r2 = read_status(w.st, &h, s);
+    int r2 = read();
     if (r2) return r2;
     if (!have_norm) {
       normx2 = h.norm2;
@@ -387,7 +427,7 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
   double nA = 0.0;
   double res_prev = 0.0;
   for (int k = 0;; ++k) {
-    sweep_enqueue(X, xdt, v, R, normx2, o.resid_mode, w, s, k & 1, n2p);
+    sweep_enqueue(X, xdt, v, R, normx2, form, w, s, k & 1, n2p);
     mr.sweeps++;
     if (defer && k == 0) {
       // sweep 1 starts from L_1, prepared speculatively by sweep 0
@@ -415,8 +455,11 @@ int mode_solve(const void* X, int xdt, const View& v, int R, const Opts& o, doub
     std::swap(w.L, w.Lnext);
     res_prev = res;
   }
+  if (defer_qr) {
+    qr_enqueue(w.L, v.I, R, U64, w.Q1, &w.st->qr_status, s);
+    return TK_OK;
+  }
   qr_enqueue(w.L, v.I, R, U64, w.Q1, &w.st->status, s);
-  if (defer_qr) return TK_OK;
   rc = read_status(w.st, &h, s);
   if (rc) return rc;
   return h.status;
@@ -457,7 +500,8 @@ int svec_enqueue(const void* X, int xdt, const View& v, int R, const double* Q, 
   DevStatus h{};
   int rc = read_status(w.st, &h, s);
   if (rc) return rc;
-  return h.status;
+  // the deferred check of the QR that made Q
+  return h.qr_status ? h.qr_status : h.status;
 }
 
 // ---------------------------------------------------------------------------
@@ -554,6 +598,17 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   Arena mar(ar.base + ar.off, ar.cap - ar.off);
   HIPCHK(hipMemsetAsync(cst, 0, sizeof(DevStatus), s));
 
+  int mstat[TK_MAX_ORDER];
+  for (int n = 0; n < N; ++n) mstat[n] = TK_SKIPPED;
+  // On a failure: its mode's status, TK_SKIPPED stays on the modes not reached.
+  auto fail = [&](int n, int code) -> int {
+    mstat[n] = code;
+    if (info) {
+      for (int k = 0; k < N; ++k) info->mode_status[k] = mstat[k];
+      info->status = code;
+    }
+    return code;
+  };
   // ||A||^2 (E5.01 uses the input's norm for every mode) comes out of the
   // first mode's initial pass over A; in st-HOSVD each later mode's initial
   // pass yields ||B||^2 of the truncated tensor it sweeps.
@@ -563,6 +618,7 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   for (int k = 0; k < N; ++k) cur[k] = dims[k];
   const void* B = A;
   int bdt = adt;
+  int prev = -1;  // the mode whose final QR is checked by the next read
   for (int t = 0; t < N; ++t) {
     const int n = order ? order[t] : t;
     View v = mode_view(N, which == 1 ? cur : dims, n);
@@ -573,8 +629,9 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
     w.st = cst;
     ModeResult mr;
     double normb2 = (which == 1 && t > 0) ? -1.0 : norm2;
+    const void* L0 = o.init_U ? o.init_U[n] : nullptr;
     rc = mode_solve(which == 1 ? B : A, which == 1 ? bdt : adt, v, R, o, normb2,
-                    norm2 >= 0.0 ? sqrt(norm2) : -1.0, n, w, U64[n], mr, s, nullptr, true);
+                    norm2 >= 0.0 ? sqrt(norm2) : -1.0, n, w, U64[n], mr, s, L0, cdt, true);
     if (rc == TK_OK && norm2 < 0.0) {
       norm2 = normb2;
       if (info) info->norm_a = sqrt(norm2);
@@ -583,20 +640,19 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
       info->iters[n] = mr.iters;
       info->converged[n] = mr.converged;
       info->resid[n] = mr.resid;
+      info->resid_form[n] = mr.form;
       info->sweeps += mr.sweeps;
     }
-    if (rc < 0) {
-      if (info) info->status = rc;
-      return rc;
-    }
+    if (mr.qr_failed && prev >= 0) return fail(prev, rc);
+    if (rc < 0) return fail(n, rc);
+    mstat[n] = mr.converged ? TK_OK : TK_NOT_CONVERGED;
     if (!mr.converged) worst = TK_NOT_CONVERGED;
+    prev = n;
     const double* Uf = U64[n];
     if (which == 0 && o.svec) {
       rc = svec_enqueue(A, adt, v, R, U64[n], w, s);
-      if (rc) {
-        if (info) info->status = rc;
-        return rc;
-      }
+      if (rc) return fail(n, rc);
+      prev = -1;
       Uf = w.Lnext;
     }
     // factor in the caller's dtype
@@ -607,7 +663,7 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
       // B <- B x_n U_n^T (equals Algorithm 3.5's R_hat R^T)
       void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
       rc = ttm_enqueue(B, bdt, N, cur, n, U[n], R, 1, dst, s);
-      if (rc) return rc;
+      if (rc) return fail(n, rc);
       cur[n] = R;
       B = dst;
       bdt = cdt;
@@ -618,7 +674,7 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
     for (int t = 0; t < N; ++t) {
       void* dst = (t == N - 1) ? G : ((t % 2 == 0) ? bufA : bufB);
       rc = ttm_enqueue(B, bdt, N, cur, t, U[t], ranks[t], 1, dst, s);
-      if (rc) return rc;
+      if (rc) return fail(t, rc);
       cur[t] = ranks[t];
       B = dst;
       bdt = cdt;
@@ -627,13 +683,14 @@ int run_driver(int which, const void* A, int32_t adt, int32_t N, const int64_t* 
   // the last mode's QR status (the read also waits for the whole stream)
   DevStatus h{};
   rc = read_status(cst, &h, s);
-  if (rc) return rc;
-  HIPCHK(hipGetLastError());
-  if (h.status) {
-    if (info) info->status = h.status;
-    return h.status;
+  if (rc) return fail(prev >= 0 ? prev : (order ? order[N - 1] : N - 1), rc);
+  if (h.qr_status && prev >= 0) return fail(prev, h.qr_status);
+  if (hipGetLastError() != hipSuccess) return fail(order ? order[N - 1] : N - 1, TK_ERR_HIP);
+  if (h.status) return fail(order ? order[N - 1] : N - 1, h.status);
+  if (info) {
+    for (int k = 0; k < N; ++k) info->mode_status[k] = mstat[k];
+    info->status = worst;
   }
-  if (info) info->status = worst;
   return worst;
 }
 
@@ -765,7 +822,7 @@ int run_hooi(const void* A, int32_t adt, int32_t N, const int64_t* dims, const i
       carve_mode(tmp, bdt, v, R, w);
       ModeResult mr;
       double ny2 = -1.0;
-      rc = mode_solve(B, bdt, v, R, o, ny2, nA, n, w, U64[n], mr, s, U64[n]);
+      rc = mode_solve(B, bdt, v, R, o, ny2, nA, n, w, U64[n], mr, s, U64[n], TK_F64);
       if (info) info->sweeps += mr.sweeps;
       if (rc < 0) {
         if (info) info->status = rc;
@@ -807,6 +864,7 @@ const char* tk_status_string(int32_t st) {
   switch (st) {
     case TK_OK: return "TK_OK";
     case TK_NOT_CONVERGED: return "TK_NOT_CONVERGED";
+    case TK_SKIPPED: return "TK_SKIPPED";
     case TK_ERR_INVALID_ARG: return "TK_ERR_INVALID_ARG";
     case TK_ERR_UNSUPPORTED_DTYPE: return "TK_ERR_UNSUPPORTED_DTYPE";
     case TK_ERR_WORKSPACE_TOO_SMALL: return "TK_ERR_WORKSPACE_TOO_SMALL";
@@ -1059,8 +1117,7 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
 
 int qr_f64(const void* L, int64_t m, int32_t r, void* Q, void* Rhat, void* ws, size_t ws_bytes,
            void* stream) {
-  (void)Rhat;
-  if (!L || !Q || m < 1 || r < 1 || r > 64 || r > m) return TK_ERR_INVALID_ARG;
+  if (!L || !Q || Rhat || m < 1 || r < 1 || r > 64 || r > m) return TK_ERR_INVALID_ARG;
   size_t need = align_up(m * (size_t)r * 8) + 2 * align_up(64 * 64 * 8) + align_up(64);
   if (!ws || ws_bytes < need) return TK_ERR_WORKSPACE_TOO_SMALL;
   Arena ar(ws, ws_bytes);
@@ -1281,7 +1338,8 @@ int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t count,
   L.U = (float*)U_packed; L.G = (float*)G_packed;
   L.status = dstatus; L.iters = diters; L.queue = queue;
   L.scratch = scratch; L.slot_bytes = (int64_t)plan.slot_bytes; L.belems = plan.belems;
-  L.tol = o.tol; L.max_iters = o.max_iters; L.seed = o.seed; L.nwg = plan.nwg;
+  L.tol = o.tol; L.max_iters = o.max_iters; L.resid_mode = o.resid_mode; L.seed = o.seed;
+  L.nwg = plan.nwg;
   const std::string key = tune_key(count, dims3, ranks3);
   int cfg = tune_lookup(key);
   if (cfg < 0) {

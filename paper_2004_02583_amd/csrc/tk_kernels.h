@@ -150,7 +150,7 @@ struct BatchLaunch {
   float* U; float* G;
   int32_t* status; int32_t* iters; int* queue;
   char* scratch; int64_t slot_bytes, belems;
-  double tol; int max_iters; uint64_t seed;
+  double tol; int max_iters; int resid_mode; uint64_t seed;
   int nwg;
 };
 constexpr int BATCHED_CONFIGS = 4;

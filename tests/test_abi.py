@@ -75,8 +75,14 @@ def test_driver_validation(lib, name):
     o.resid_mode = 4
     assert _drv(lib, fn, opts=o) == -1
     o.resid_mode = 0
+    o.compute = 1                                       # only TK_COMPUTE_AS_STORAGE
+    assert _drv(lib, fn, opts=o) == -2
+    o.compute = 0
     o.struct_size = 8
     assert _drv(lib, fn, opts=o) == -1
+    # R_n <= 64: the r x r small linear algebra runs in one workgroup
+    assert _drv(lib, fn, dims=(70, 70, 3), ranks=(65, 65, 2)) == -1
+    assert _drv(lib, fn, dims=(70, 70, 3), ranks=(64, 64, 2), ws_bytes=16) == -3
 
 
 def test_bad_order(lib):
@@ -136,7 +142,13 @@ def test_reconstruct_contract_step_validation(lib):
                              16, None) == -3
     assert lib.als_sweep_step(FAKE, 1, 3, d, 1, 2, FAKE, FAKE, 1.0, 3, ctypes.byref(n2), FAKE,
                               1 << 30, None) == -1         # resid mode
+    assert lib.als_sweep_step(FAKE, 1, 3, d, 1, 2, FAKE, FAKE, 1.0, L.TK_RESID_AUTO,
+                              ctypes.byref(n2), FAKE, 1 << 30, None) == -1   # AUTO: drivers only
     assert lib.qr_f64(FAKE, 3, 4, FAKE, None, FAKE, 1 << 20, None) == -1   # r > m
+    assert lib.qr_f64(FAKE, 30, 4, FAKE, FAKE, FAKE, 1 << 20, None) == -1  # Rhat reserved
+    assert lib.qr_f64(FAKE, 100, 65, FAKE, None, FAKE, 1 << 20, None) == -1  # r > 64
+    assert lib.contract_allbut(FAKE, FAKE, 1, 3, L.i64arr([4, 5, 70]), 2, 65, FAKE, FAKE,
+                               1 << 30, None) == -1       # J > 64
     assert lib.qr_f64(FAKE, 30, 4, FAKE, None, FAKE, 16, None) == -3
 
 
@@ -211,3 +223,48 @@ def test_hooi_validation(lib):
     need = lib.hooi_workspace_bytes(1, 3, dims, ranks)
     assert need >= lib.als_workspace_bytes(1, 1, 3, dims, ranks)
     assert lib.hooi_workspace_bytes(1, 3, dims, L.i32arr((9, 3, 4))) == 0
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes structures of the binding have the header's layout: a C
+    program compiled against include/tucker_als.h prints sizeof and every
+    field offset."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tk_als_opts": L.tk_als_opts, "tk_als_info": L.tk_als_info,
+               "tk_hooi_info": L.tk_hooi_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tucker_als.h"',
+             "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = []
+    for name, cls in structs.items():
+        want.append(f"{name} size {ctypes.sizeof(cls)}")
+        for fname, _ in cls._fields_:
+            want.append(f"{name} {fname} {getattr(cls, fname).offset}")
+    assert [g for g in got if g] == want
+
+
+def test_enum_values_match_header():
+    """Status, dtype and residual-mode values of the binding equal the header's."""
+    src = open(HEADER).read()
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(TK_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    assert vals["TK_F64"] == L.TK_F64 and vals["TK_F32"] == L.TK_F32 and vals["TK_BF16"] == L.TK_BF16
+    assert vals["TK_RESID_AUTO"] == L.TK_RESID_AUTO
+    assert vals["TK_RESID_TRACE"] == L.TK_RESID_TRACE
+    assert vals["TK_RESID_EXPLICIT"] == L.TK_RESID_EXPLICIT
+    assert vals["TK_COMPUTE_AS_STORAGE"] == L.TK_COMPUTE_AS_STORAGE
+    for code, name in L.STATUS.items():
+        assert vals[name] == code
