@@ -174,6 +174,29 @@ TK_API int als_sthosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t*
                 void* G, void* ws, size_t ws_bytes, tk_als_info* info,
                 void* stream);
 
+/* als_sthosvd_noalloc -- als_sthosvd for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same computation, kernels and results, with the
+ * workspace taken from a device array inside the library instead of `ws`.
+ * That array holds als_sthosvd_noalloc_max_bytes() bytes (64 MiB) per GPU,
+ * exists on every GPU the library runs on until the process ends, and is
+ * found on the current device (`stream` must belong to it).  The call
+ * allocates nothing (no hipMalloc, hipFree, pinned host buffer or library
+ * routine that allocates) and reads its status block through pageable host
+ * memory unless this thread already holds the pinned buffer of an earlier
+ * als_* call.  Shapes whose als_workspace_bytes(1, ...) exceeds the array
+ * return TK_ERR_WORKSPACE_TOO_SMALL before any device work.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * host threads, or work still running on another stream) race and must be
+ * serialised by the caller.  Arguments and return values otherwise as for
+ * als_sthosvd. */
+TK_API int als_sthosvd_noalloc(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                               const int32_t* ranks, const tk_als_opts* opts, void* const* U,
+                               void* G, tk_als_info* info, void* stream);
+
+/* Size in bytes of the device array als_sthosvd_noalloc works in. */
+TK_API size_t als_sthosvd_noalloc_max_bytes(void);
+
 /* als_thosvd -- Algorithm 3.4 (t-HOSVD-ALS): the per-mode ALS + QR of
  * als_sthosvd on the unchanged A for every mode, then
  * G = A x_1 U_1^T ... x_N U_N^T (Section 2, eq. best).  Arguments as for

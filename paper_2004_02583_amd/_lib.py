@@ -30,7 +30,7 @@ EXPORTS = [
     "contract_allbut", "contract_allbut_workspace_bytes", "als_init_step",
     "als_sweep_step", "als_sweep_kernel", "qr_f64", "als_sthosvd_batched",
     "als_sthosvd_batched_workspace_bytes", "hooi_refine", "hooi_workspace_bytes",
-    "st_order_auto", "tk_status_string",
+    "st_order_auto", "tk_status_string", "als_sthosvd_noalloc", "als_sthosvd_noalloc_max_bytes",
 ]
 
 
@@ -97,6 +97,12 @@ def _declare(lib):
     lib.als_sthosvd.argtypes = drv
     lib.als_thosvd.argtypes = drv
     lib.als_sthosvd.restype = lib.als_thosvd.restype = _I32
+    lib.als_sthosvd_noalloc.argtypes = [_P, _I32, _I32, _PI64, _PI32,
+                                        ctypes.POINTER(tk_als_opts), ctypes.POINTER(_P), _P,
+                                        ctypes.POINTER(tk_als_info), _P]
+    lib.als_sthosvd_noalloc.restype = _I32
+    lib.als_sthosvd_noalloc_max_bytes.argtypes = []
+    lib.als_sthosvd_noalloc_max_bytes.restype = _SZ
     lib.als_workspace_bytes.argtypes = [_I32, _I32, _I32, _PI64, _PI32]
     lib.als_workspace_bytes.restype = _SZ
     lib.ttm.argtypes = [_P, _I32, _I32, _PI64, _I32, _P, _I32, _I64, _I32, _P, _I32, _P]

@@ -193,10 +193,14 @@ void qr_enqueue(const double* L, int64_t m, int r, double* Q, double* Q1, int* s
 // thread (allocated on first use, kept for the life of the thread: a copy
 // into pageable memory goes through a runtime staging buffer and costs a
 // longer round trip on every sweep).
+// While a call of the allocation-free entry point runs on this thread, the
+// buffer is not allocated (an earlier allocation is still used).
+thread_local bool t_no_alloc = false;
+
 DevStatus* pinned_status() {
   thread_local DevStatus* p = nullptr;
   thread_local bool tried = false;
-  if (!tried) {
+  if (!tried && !t_no_alloc) {
     tried = true;
     if (hipHostMalloc((void**)&p, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) p = nullptr;
   }
@@ -927,6 +931,69 @@ int als_sthosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
                 const int32_t* ranks, const tk_als_opts* opts, void* const* U, void* G,
                 void* ws, size_t ws_bytes, tk_als_info* info, void* stream) {
   return run_driver(1, A, a_dtype, N, dims, ranks, opts, U, G, ws, ws_bytes, info, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free st-HOSVD-ALS: the workspace is a file-scope device array, one
+// copy per GPU, held until the process ends.  In host code `scratch` only names
+// the symbol; its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept.
+namespace tk {
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex& scratch_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
+int scratch_address(void** out) {
+  static void* addr[NOALLOC_MAX_DEVICES] = {nullptr};
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return TK_ERR_HIP;
+  std::lock_guard<std::mutex> g(scratch_mutex());
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+extern "C" {
+
+size_t als_sthosvd_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+int als_sthosvd_noalloc(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,
+                        const int32_t* ranks, const tk_als_opts* opts, void* const* U, void* G,
+                        tk_als_info* info, void* stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (!valid_dtype(a_dtype)) return TK_ERR_UNSUPPORTED_DTYPE;
+  if (!A || !U || !G || !valid_dims(N, dims) || !valid_ranks(N, dims, ranks))
+    return TK_ERR_INVALID_ARG;
+  if (driver_ws(1, a_dtype, N, dims, ranks) > NOALLOC_SCRATCH_BYTES)
+    return TK_ERR_WORKSPACE_TOO_SMALL;
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  struct NoAlloc {
+    bool prev;
+    NoAlloc() : prev(t_no_alloc) { t_no_alloc = true; }
+    ~NoAlloc() { t_no_alloc = prev; }
+  } guard;
+  return run_driver(1, A, a_dtype, N, dims, ranks, opts, U, G, ws, NOALLOC_SCRATCH_BYTES, info,
+                    stream);
 }
 
 int als_thosvd(const void* A, int32_t a_dtype, int32_t N, const int64_t* dims,

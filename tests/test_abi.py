@@ -268,3 +268,18 @@ def test_enum_values_match_header():
     assert vals["TK_COMPUTE_AS_STORAGE"] == L.TK_COMPUTE_AS_STORAGE
     for code, name in L.STATUS.items():
         assert vals[name] == code
+
+
+def test_noalloc_validation(lib):
+    """The allocation-free entry point rejects bad arguments and shapes beyond its
+    device array before any HIP call."""
+    U = L.ptrarr([0x100000] * 3)
+    d, r = L.i64arr([8, 9, 10]), L.i32arr([2, 3, 4])
+    assert lib.als_sthosvd_noalloc_max_bytes() == 64 << 20
+    assert lib.als_sthosvd_noalloc(FAKE, 7, 3, d, r, None, U, FAKE, None, None) == -2
+    assert lib.als_sthosvd_noalloc(None, 1, 3, d, r, None, U, FAKE, None, None) == -1
+    assert lib.als_sthosvd_noalloc(FAKE, 1, 3, d, L.i32arr([9, 3, 4]), None, U, FAKE, None,
+                                   None) == -1
+    big, rb = L.i64arr([400, 400, 400]), L.i32arr([40, 40, 40])
+    assert lib.als_workspace_bytes(1, 1, 3, big, rb) > lib.als_sthosvd_noalloc_max_bytes()
+    assert lib.als_sthosvd_noalloc(FAKE, 1, 3, big, rb, None, U, FAKE, None, None) == -3
