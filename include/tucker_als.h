@@ -308,8 +308,12 @@ TK_API int qr_f64(const void* L, int64_t m, int32_t r, void* Q, void* Rhat,
  * Lacc = A_(mode) V (FP64 I_mode x R).  When `reduce` is 0 only the
  * streaming kernel runs and leaves per-workgroup partials in ws (Lacc and
  * GV are untouched); with 1 the partials are summed in a fixed order into
- * Lacc and GV.  Shapes outside the fused kernel's range (FP64 storage,
- * I_mode > 256, R > 48) use the two-pass kernels.  a_dtype F32 or BF16.
+ * Lacc and GV.  For BF16 storage Lq is first rounded to BF16 precision
+ * (round to nearest even), as the drivers quantise L~ for BF16 sweeps with
+ * the trace residual (which uses the Gram of the rounded values):
+ * V = A^T round(Lq).
+ * Shapes outside the fused kernels' range (FP64 storage, I_mode > 1024,
+ * R > 48) use the two-pass kernels.  a_dtype F32 or BF16.
  * ws >= als_workspace_bytes(1, ...) for a tensor of these dims with all
  * ranks equal to R.  Asynchronous on `stream`. */
 TK_API int als_sweep_kernel(const void* A, int32_t a_dtype, int32_t N,

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtucker_als.so")
 SOURCES = ["tk_api.hip", "k_small_la.hip", "k_mode_step.hip", "k_stream.hip", "k_fused.hip",
-           "k_fused_bf16.hip", "k_fused_big.hip", "k_batched.hip",
+           "k_fused_bf16.hip", "k_fused_big.hip", "k_fused_bf16_big.hip", "k_batched.hip",
            "k_svec.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = ["--offload-arch=gfx950"]

@@ -12,6 +12,10 @@
 // accumulation differs from the FP32 matrix-core path.  G_V stays on the
 // FP32 matrix cores from the FP32 V (the trace residual needs it).
 //
+// A sweep whose Lq is already rounded to BF16 precision (the drivers quantise
+// L~ so for BF16 storage, the trace residual taking the Gram of the rounded
+// values) multiplies by its single BF16 term instead of three.
+//
 // Work layout: 256 persistent workgroups of 8 waves walk tiles of TJ = 128
 // fibres (view [P, I, Q] with Q even: each lane loads one dword holding two
 // adjacent fibres of a row).  The tile is kept in LDS as BF16 rows whose
@@ -123,8 +127,9 @@ __device__ __forceinline__ void stash(const View& v, int lane, int w, const uint
   if (NORM) nsum += (ns[0] + ns[1]) + (ns[2] + ns[3]);
 }
 
-// MODE 0: sweep; 2: init (sketch, norm, no Gram); 3: TTM.
-template <int NR, int MODE, int IC>
+// MODE 0: sweep; 2: init (sketch, norm, no Gram); 3: TTM.  NS: BF16 terms of
+// Lq in the R-update (1 when the Lq values are BF16-representable, else 3).
+template <int NR, int MODE, int IC, int NS>
 __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int RP = 16 * NR;
@@ -212,7 +217,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
 #pragma unroll
-          for (int s = 0; s < 3; ++s) {
+          for (int s = 0; s < NS; ++s) {
             const bf8 bv = *(const bf8*)(Lq + (s * RP + 16 * n + lr) * LS + row0);
             vacc[n] = mfma_bf16(av, bv, vacc[n]);
           }
@@ -399,7 +404,7 @@ __host__ __device__ inline LdsB lds_b16r(int IC, int NR, int mode) {
   return l;
 }
 
-template <int NR, int MODE, int IC>
+template <int NR, int MODE, int IC, int NS>
 __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int RP = 16 * NR;
@@ -426,8 +431,9 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
 
   for (int e = threadIdx.x; e < xbuf; e += NT) Xs32[e] = 0u;   // both buffers
 
-  // Lq^T splits of rank 16 nw + lr, rows 32 st + 8 lk + e, as B operands
-  bf8 bq[STM][3];
+  // Lq^T splits of rank 16 nw + lr, rows 32 st + 8 lk + e, as B operands (the
+  // first NS of the three)
+  bf8 bq[STM][NS];
   if (MODE != 2) {
     const int64_t ldi = a.lq_ldi ? a.lq_ldi : R, ldo = a.lq_ldi ? a.lq_ldo : 1;
     const int r = 16 * nw + lr;
@@ -437,11 +443,10 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
       for (int e = 0; e < 8; ++e) {
         const int row = 32 * st + 8 * lk + e;
         const float x = (row < I && r < R) ? a.Lq[row * ldi + r * ldo] : 0.0f;
-        __bf16 h, m, l;
-        split3(x, h, m, l);
-        bq[st][0][e] = h;
-        bq[st][1][e] = m;
-        bq[st][2][e] = l;
+        __bf16 sp[3];
+        split3(x, sp[0], sp[1], sp[2]);
+#pragma unroll
+        for (int s3 = 0; s3 < NS; ++s3) bq[st][s3][e] = sp[s3];
       }
     }
   }
@@ -497,7 +502,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
 #pragma unroll
           for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
 #pragma unroll
-          for (int s3 = 0; s3 < 3; ++s3) vacc[b] = mfma_bf16(av, bq[st][s3], vacc[b]);
+          for (int s3 = 0; s3 < NS; ++s3) vacc[b] = mfma_bf16(av, bq[st][s3], vacc[b]);
         }
       }
       // V[16 fb + 4 lk + q][16 nw + lr] = vacc[b][q]
@@ -663,33 +668,41 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   }
 }
 
-template <int NR, int MODE, int IC>
+template <int NR, int MODE, int IC, int NS>
 void launch3r(const FusedArgs& a, int nwg, hipStream_t s) {
   const size_t bytes = (size_t)lds_b16r(IC, NR, MODE).total;
-  (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC>,
+  (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC, NS>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC>), dim3(nwg), dim3(NT), bytes, s, a);
+  hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC, NS>), dim3(nwg), dim3(NT), bytes, s, a);
 }
 
-template <int NR, int MODE, int IC>
+template <int NR, int MODE, int IC, int NS>
 void launch3(const FusedArgs& a, int nwg, hipStream_t s) {
   const size_t bytes = (size_t)lds_b16((int)a.v.I, NR, MODE).total;
-  (void)hipFuncSetAttribute((const void*)k_fused_bf16<NR, MODE, IC>,
+  (void)hipFuncSetAttribute((const void*)k_fused_bf16<NR, MODE, IC, NS>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  hipLaunchKernelGGL((k_fused_bf16<NR, MODE, IC>), dim3(nwg), dim3(NT), bytes, s, a);
+  hipLaunchKernelGGL((k_fused_bf16<NR, MODE, IC, NS>), dim3(nwg), dim3(NT), bytes, s, a);
+}
+
+// NS = 1 for sweeps whose Lq is BF16-representable (the drivers round it so);
+// the TTM and other callers pass FP32 operands, split in three.
+template <int NR, int MODE, int NS>
+void launch2s(const FusedArgs& a, int nwg, hipStream_t s) {
+  if (NR <= 2 && a.v.I <= XR_MAX_R) {
+    if (a.v.I <= 64) launch3r<NR <= 2 ? NR : 2, MODE, 8, NS>(a, nwg, s);
+    else if (a.v.I <= 128) launch3r<NR <= 2 ? NR : 2, MODE, 16, NS>(a, nwg, s);
+    else launch3r<NR <= 2 ? NR : 2, MODE, 32, NS>(a, nwg, s);
+    return;
+  }
+  if (a.v.I <= 64) launch3<NR, MODE, 8, NS>(a, nwg, s);
+  else if (a.v.I <= 128) launch3<NR, MODE, 16, NS>(a, nwg, s);
+  else launch3<NR, MODE, 32, NS>(a, nwg, s);
 }
 
 template <int NR, int MODE>
 void launch2(const FusedArgs& a, int nwg, hipStream_t s) {
-  if (NR <= 2 && a.v.I <= XR_MAX_R) {
-    if (a.v.I <= 64) launch3r<NR <= 2 ? NR : 2, MODE, 8>(a, nwg, s);
-    else if (a.v.I <= 128) launch3r<NR <= 2 ? NR : 2, MODE, 16>(a, nwg, s);
-    else launch3r<NR <= 2 ? NR : 2, MODE, 32>(a, nwg, s);
-    return;
-  }
-  if (a.v.I <= 64) launch3<NR, MODE, 8>(a, nwg, s);
-  else if (a.v.I <= 128) launch3<NR, MODE, 16>(a, nwg, s);
-  else launch3<NR, MODE, 32>(a, nwg, s);
+  if (MODE == 0 && a.lq_bf16) launch2s<NR, MODE, 1>(a, nwg, s);
+  else launch2s<NR, MODE, 3>(a, nwg, s);
 }
 
 template <int NR>

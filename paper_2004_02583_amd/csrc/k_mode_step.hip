@@ -7,7 +7,9 @@
 //   QR     reduced QR of a tall matrix by CholeskyQR2 (diag(R_hat) > 0),
 //          used for the initial guess (Section 5) and the returned factor;
 //   PREP   for the next sweep: L~ = L (L^T L)^{-1} quantised to the compute
-//          type, the inverse Cholesky factor of the Gram of the quantised L~
+//          type (to BF16 precision for BF16 storage, whose sweeps multiply
+//          the BF16 tensor by L~ as one BF16 term), the inverse Cholesky
+//          factor of the Gram of the quantised L~
 //          and, for the explicit residual, L in the compute type.
 // Every r x r Gram G is factored by one Gaussian elimination of [G | I]
 // without pivoting (G = Lu Dp Lu^T): the pivots Dp give the test of Remark 3
@@ -229,9 +231,12 @@ __device__ void bwtw(const ldsd* W, int r, int ld, ldsd* M) {
 // at the end.
 enum { W_NONE = 0, W_M = 1, W_BT = 2 };
 
+// With rbf16 the product written to Outp (and kept for the Gram) is rounded to
+// BF16 precision (round to nearest even) before it is stored in TO.
 template <typename TO>
 __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restrict__ S, int64_t m,
-                                            int wsel, TO* Outp, TO* Out2p, bool gram) {
+                                            int wsel, TO* Outp, TO* Out2p, bool gram,
+                                            bool rbf16 = false) {
   const int r = L.r, ld = L.ld, tr = L.tr;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -346,7 +351,8 @@ __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restri
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
                 const int orow = 16 * rt + lk + 4 * v;
-                const TO q = Store<TO>::cvt(acc[v]);
+                TO q = Store<TO>::cvt(acc[v]);
+                if (rbf16) q = (TO)bf16_to_f32(f32_to_bf16((float)q));
                 To[orow * ld + col] = (double)q;
                 if (Outp && orow < rows) Out[(i0 + orow) * r + col] = q;
               }
@@ -486,8 +492,9 @@ __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
     }
     bscale(L.A, L.B, r, ld);
     bwtw(L.B, r, ld, L.M);
-    // L~ = L (L^T L)^{-1} in TQ, with the Gram of the quantised L~
-    stream_pass<TQ>(L, src, m, W_M, (TQ*)a.Lq, (TQ*)a.Lr, true);
+    // L~ = L (L^T L)^{-1} in TQ (BF16 precision with lq_bf16), with the Gram
+    // of the quantised L~
+    stream_pass<TQ>(L, src, m, W_M, (TQ*)a.Lq, (TQ*)a.Lr, true, a.lq_bf16 != 0);
     if (belim(L.A, L.B, r, ld)) {
       if (tid == 0) *pst = TK_ERR_RANK_DEFICIENT;
       return;

@@ -62,8 +62,18 @@ __global__ void k_widen(const T* __restrict__ in, int64_t n, double* __restrict_
   if (e < n) out[e] = (double)in[e];
 }
 
+// Rounds FP32 values to BF16 precision (round to nearest even), in place.
+__global__ void k_round_bf16(float* __restrict__ x, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = bf16_to_f32(f32_to_bf16(x[e]));
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
+
+void launch_round_bf16(float* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, n);
+}
 
 template <typename T>
 void launch_reduce_parts(const T* in, int parts, int64_t n, int64_t stride, double* out,

@@ -246,6 +246,15 @@ int resolve_resid_form(int resid_mode, int xdt, const View& v, double tol) {
   return crit > 1e-4 * tol ? TK_RESID_EXPLICIT : TK_RESID_TRACE;
 }
 
+// BF16 sweeps with the trace residual multiply the BF16 tensor by L~ rounded to
+// BF16 precision (one BF16 term; the trace form takes the Gram of the rounded
+// values, so it is the residual of exactly the subspace swept).  The explicit
+// residual sums ||a_j - L v_j||^2 with L itself, which is consistent with v_j
+// only for the FP32 L~ (three BF16 terms): there L~ is not rounded.
+inline bool lq_rounded(int xdt, int resid_form) {
+  return xdt == TK_BF16 && resid_form == TK_RESID_TRACE;
+}
+
 // Y (FP64, I x R) = B_(n) S  (Section 5 initial sketch), partial-reduced;
 // with norm2 != null the same pass also yields ||B||_F^2.
 void init_enqueue(const void* X, int xdt, const View& v, int R, uint64_t seed, int mode,
@@ -285,6 +294,7 @@ void init_finish_enqueue(const View& v, int R, int xdt, int resid_mode, ModeWs& 
   a.m = v.I; a.r = R; a.ops = STEP_QR | STEP_PREP;
   a.Qin = w.Lacc; a.Q1 = w.Q1; a.Qout = w.L;
   a.Lq = w.Lq; a.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; a.Wq = w.Wq;
+  a.lq_bf16 = lq_rounded(xdt, resid_mode);
   a.status = &w.st->status; a.prep_status = &w.st->prep_status[0];
   launch_mode_step(a, cdtype(xdt), s);
 }
@@ -306,6 +316,7 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
     FusedArgs f{};
     f.X = X; f.x_dtype = xdt; f.v = v; f.R = R;
     f.Lq = (const float*)w.Lq;
+    f.lq_bf16 = lq_rounded(xdt, resid_mode);   // the preparation rounded L~ so
     f.Lr = expl ? (const float*)w.Lr : nullptr;
     f.lacc_parts = (float*)w.parts;
     f.gv_parts = w.gparts;
@@ -345,6 +356,7 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
   }
   a.res2 = w.st->res[slot];
   a.Lq = w.Lq; a.Lr = expl ? w.Lr : nullptr; a.Wq = w.Wq;
+  a.lq_bf16 = lq_rounded(xdt, resid_mode);
   a.status = &w.st->status; a.prep_status = &w.st->prep_status[slot];
   launch_mode_step(a, cdt, s);
 }
@@ -1170,6 +1182,7 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
     p.m = v.I; p.r = R; p.ops = STEP_PREP;
     p.Qin = w.L;
     p.Lq = w.Lq; p.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; p.Wq = w.Wq;
+    p.lq_bf16 = lq_rounded(a_dtype, resid_mode);
     p.status = &w.st->status; p.prep_status = &w.st->prep_status[0];
     launch_mode_step(p, cdtype(a_dtype), s);
   }
@@ -1465,10 +1478,18 @@ extern "C" int als_sweep_kernel(const void* A, int32_t a_dtype, int32_t N, const
   carve_mode(ar, a_dtype, v, R, w);
   hipStream_t s = (hipStream_t)stream;
   const int64_t IR = v.I * (int64_t)R;
+  if (a_dtype == TK_BF16) {
+    // BF16 sweeps multiply by L~ rounded to BF16 precision (as the drivers
+    // prepare it): round a copy
+    HIPCHK(hipMemcpyAsync(w.Lr, Lq, (size_t)IR * 4, hipMemcpyDeviceToDevice, s));
+    launch_round_bf16((float*)w.Lr, IR, s);
+    Lq = (const float*)w.Lr;
+  }
   if (fused_supported(a_dtype, v, R, TK_RESID_TRACE)) {
     FusedArgs f{};
     f.X = A; f.x_dtype = a_dtype; f.v = v; f.R = R;
     f.Lq = Lq;
+    f.lq_bf16 = a_dtype == TK_BF16;
     f.lacc_parts = (float*)w.parts;
     f.gv_parts = w.gparts;
     int nwg = launch_fused(f, NWG_MAX, s);

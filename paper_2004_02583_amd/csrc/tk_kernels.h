@@ -102,6 +102,8 @@ struct FusedArgs {
   double* gv_parts;      // [FUSED_WAVES * nwg][R][R]
   double* resid_parts;   // [FUSED_WAVES * nwg] (explicit residual)
   int sketch; uint64_t seed; int mode;  // init variant: V = sketch, no G_V
+  int lq_bf16;           // the Lq values are BF16-representable (BF16 sweeps
+                         // multiply by them as one BF16 term)
   double* norm2_parts;   // [FUSED_WAVES * nwg] sums of X^2 (init variant, optional)
   float* y;              // TTM output (or null)
   int64_t lq_ldi, lq_ldo;
@@ -118,6 +120,14 @@ int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
 // launch_fused when it takes the shape; same partial-buffer layout.
 bool fused_bf16_supported(const FusedArgs& a, int mode);
 int launch_fused_bf16(const FusedArgs& a, int mode, int nwg_max, hipStream_t s);
+// BF16 storage, modes of 256 < I <= 1024 rows, R <= 48, sweep with
+// BF16-representable Lq: on the BF16 matrix cores, Lq resident in LDS, the
+// fibres streamed in chunks of rows; used by launch_fused when it takes the
+// shape.
+bool fused_bf16_big_supported(const FusedArgs& a, int mode);
+int launch_fused_bf16_big(const FusedArgs& a, int nwg_max, hipStream_t s);
+// Rounds n FP32 values to BF16 precision in place (round to nearest even).
+void launch_round_bf16(float* x, int64_t n, hipStream_t s);
 // Modes of 256 < I <= 1024 rows (R <= 48; sweep, init, TTM), streamed in
 // chunks of rows: used by launch_fused when it takes the shape.
 bool fused_big_shape(int x_dtype, const View& v, int64_t R, int mode);
@@ -135,9 +145,10 @@ struct StepArgs {
   // QR: Qout = Q of the reduced QR of Qin (Q1: m x r scratch)
   const double* Qin; double* Q1; double* Qout;
   // PREP from Lnext (SOLVE) or Qout (QR): Lq = L (L^T L)^{-1} in the compute
-  // type, Wq = chol(Lq^T Lq)^{-1} (r x r lower, row-major), Lr = L in the
-  // compute type (if non-null)
-  void* Lq; void* Lr; double* Wq;
+  // type (rounded to BF16 precision when lq_bf16), Wq = chol(Lq^T Lq)^{-1}
+  // (r x r lower, row-major, of the rounded Lq), Lr = L in the compute type
+  // (if non-null)
+  void* Lq; void* Lr; double* Wq; int lq_bf16;
   int* status;        // failures of SOLVE / QR / non-speculative PREP
   int* prep_status;   // failures of a speculative PREP
 };

@@ -429,7 +429,20 @@ KERNEL_CASES = [
     ((20, 200, 50), 1, 17),     # 16 < R <= 20 (second rank tile mostly padding), Q < 64
     ((30, 40, 200), 2, 19),     # 16 < R <= 20, Q == 1
     ((64, 37, 70), 1, 18),      # 16 < R <= 20, ragged small mode
+    # BF16 storage, 256 < I <= 1024: the BF16-matrix-core large-mode sweep
+    ((16, 520, 24), 1, 48),     # R = 48, five chunks (the last ragged), Q = 24
+    ((48, 264, 16), 1, 33),     # R = 33 (third rank tile mostly padding), last chunk 8 rows
+    ((33, 392), 1, 20),         # Q == 1 (fibres are rows), one ragged fibre tile
+    ((3, 1000, 8), 1, 5),       # R = 5, Q = 8, J = 24
+    ((2, 1024, 40), 1, 48),     # I = 1024, R = 48, ragged fibre tiles
 ]
+
+
+def bf16_round(x):
+    """Round float32 values to BF16 precision (nearest even), kept as float64."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
@@ -437,7 +450,7 @@ KERNEL_CASES = [
 def test_sweep_kernel_parity(gpu_lib, dims, mode, R, dt):
     """Lacc = A_(n) V and GV = V^T V for V = A_(n)^T Lq, against FP64 on the
     same values (FP32 accumulation: a few roundings of I-term and
-    J-term sums)."""
+    J-term sums).  For BF16 storage Lq enters rounded to BF16 precision."""
     tk = gpu_lib
     flush(f"sweep_kernel {dims} mode={mode} R={R} {dt}")
     rng = np.random.default_rng(40)
@@ -445,11 +458,12 @@ def test_sweep_kernel_parity(gpu_lib, dims, mode, R, dt):
     Lq = rng.standard_normal((dims[mode], R)).astype(np.float32)
     Lacc, GV = tk.als_sweep_kernel(to_gpu(A, dt), mode, torch.from_numpy(Lq).cuda())
     An = o.unfold(held(A, dt), mode)
-    V = An.T @ Lq.astype(np.float64)
+    Lh = bf16_round(Lq) if dt == "bf16" else Lq.astype(np.float64)
+    V = An.T @ Lh
     want_l = An @ V
     want_g = V.T @ V
     # scale-aware bounds: |V| from |A||Lq|, then |A||V|
-    Vabs = np.abs(An).T @ np.abs(Lq.astype(np.float64))
+    Vabs = np.abs(An).T @ np.abs(Lh)
     bl = (dims[mode] + 64) * 2.0 ** -24 * (np.abs(An) @ Vabs)
     bg = (dims[mode] + 64) * 2.0 ** -24 * (Vabs.T @ Vabs)
     assert np.all(np.abs(np64(Lacc) - want_l) <= 4 * bl + 1e-30)
@@ -457,20 +471,27 @@ def test_sweep_kernel_parity(gpu_lib, dims, mode, R, dt):
     np.testing.assert_array_equal(np64(GV), np64(GV).T)
 
 
+@pytest.mark.parametrize("resid", ["auto", "trace"])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 @pytest.mark.parametrize("which", ["t", "st"])
-def test_large_mode_driver_parity(gpu_lib, which, dt):
-    """A 700-row mode runs the chunked large-mode kernels (sketch, sweeps, TTM)."""
+def test_large_mode_driver_parity(gpu_lib, which, dt, resid):
+    """A 700-row mode runs the chunked large-mode kernels (sketch, sweeps, TTM); with
+    the trace residual its BF16 sweeps run on the BF16-matrix-core large-mode kernel
+    (the explicit residual, which the automatic choice takes at this J, runs the
+    two-pass kernels).  Errors against the oracle on the values the GPU holds."""
     tk = gpu_lib
-    flush(f"large-mode driver {which} {dt}")
+    flush(f"large-mode driver {which} {dt} {resid}")
     rng = np.random.default_rng(42)
-    A = synth.tucker_lowrank(rng, (700, 24, 30), (20, 6, 8), 1e-3)[0]
+    A = synth.tucker_lowrank(rng, (700, 24, 32), (20, 6, 8), 1e-3)[0]
     Ah = held(A, dt)
     run = tk.als_thosvd if which == "t" else tk.als_sthosvd
-    G, Us, info = run(to_gpu(A, dt), (20, 6, 8), tol=1e-5, seed=3)
+    G, Us, info = run(to_gpu(A, dt), (20, 6, 8), tol=1e-5, seed=3, resid_mode=resid)
     ref = (o.thosvd_als if which == "t" else o.sthosvd_als)(Ah, (20, 6, 8), tol=1e-5, seed=3)
-    gate = 1e-5 if dt == "f32" else 1e-2
-    assert abs(_relerr_of(Ah, G, Us) - o.relerr(Ah, ref.G, ref.U)) <= gate
+    flush(f"  iters gpu={info['iters']} oracle={[m.iters for m in ref.info]}")
+    assert abs(_relerr_of(Ah, G, Us) - o.relerr(Ah, ref.G, ref.U)) <= 1e-5
+    if dt == "bf16":
+        ref64 = (o.thosvd_als if which == "t" else o.sthosvd_als)(A, (20, 6, 8), tol=1e-5, seed=3)
+        assert abs(_relerr_of(A, G, Us) - o.relerr(A, ref64.G, ref64.U)) <= 1e-2
 
 
 def test_two_pass_driver_parity(gpu_lib):
