@@ -119,6 +119,40 @@ def copy_calibration(nbytes=1 << 30):
     log(f"copy calibration: 3 copies of {nbytes} bytes")
 
 
+def bench_batched(tk, steps, sample=64):
+    """The 512-tensor batched workload (I_n in [16,128], R_n in [4,16], 1e-3 noise): one
+    batched call (a replayed HIP graph of the persistent kernel) against the
+    single-tensor driver on the first ``sample`` tensors, scaled to the batch."""
+    import torch
+    from workloads import synth
+    items = synth.workload_batched(count=512)
+    As = [torch.from_numpy(it["A"]).float().cuda() for it in items]
+    ranks = [it["ranks"] for it in items]
+    plan = tk.BatchedPlan(As, ranks)
+    plan.run(tol=TOL)                       # autotune and capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(tol=TOL)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res = plan.results()
+    nbytes = sum(step_bytes(tuple(A.shape), r, it) for A, r, (_, _, it) in zip(As, ranks, res))
+    for A, r in zip(As[:sample], ranks[:sample]):
+        tk.als_sthosvd(A, r, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for A, r in zip(As[:sample], ranks[:sample]):
+        tk.als_sthosvd(A, r, tol=TOL)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) / sample * len(As)
+    log(f"batched {dt*1e3:.3f} ms, single-tensor loop {seq*1e3:.1f} ms (scaled from {sample})")
+    return dict(batched_ms=round(dt * 1e3, 3), batched_gbs=round(nbytes / dt / 1e9, 1),
+                batched_input_mb=round(plan.algorithmic_bytes_per_pass / 1e6, 1),
+                batched_single_loop_ms=round(seq * 1e3, 2),
+                batched_speedup_vs_single=round(seq / dt, 2))
+
+
 def cpu_baseline(A, ncols=8_000_000, sweeps=3):
     """Literal Algorithm 3.3 sweeps of the FP64 oracle on the first ``ncols``
     columns of the mode-1 unfolding (a 200 x ncols sample)."""
@@ -145,6 +179,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
@@ -215,6 +250,10 @@ def main():
                      bf16_speedup_vs_fp32=round(dt / dtb, 3))
         del Ab, wsb
         log(f"bf16 step {dtb*1e3:.2f} ms relerr={eb:.4e}")
+
+    if not args.no_batched:
+        log("batched st-HOSVD-ALS (512 tensors)")
+        extra.update(bench_batched(tk, args.steps))
 
     cpu = None
     if not args.no_cpu_baseline:

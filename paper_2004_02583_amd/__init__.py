@@ -19,6 +19,7 @@ from ._lib import TuckerALSError, load_library  # noqa: F401
 __all__ = [
     "als_sthosvd", "als_thosvd", "hooi", "st_order", "ttm", "tucker_reconstruct", "contract_allbut",
     "als_init_step", "als_sweep_step", "als_sweep_kernel", "qr_f64", "batched_sthosvd",
+    "BatchedPlan",
     "TuckerALSError", "load_library", "TuckerProject", "TuckerReconstruct",
 ]
 
@@ -358,60 +359,89 @@ def qr_f64(Lm):
     return Q
 
 
+class BatchedPlan:
+    """Packed device buffers of a batch of order-3 FP32 tensors for
+    ``als_sthosvd_batched``.  ``run`` decomposes the tensors in place (the
+    packed inputs stay unchanged) and can be called again: with the same
+    buffers and options the library replays the HIP graph it captured."""
+
+    def __init__(self, tensors, ranks_list):
+        lib = L.lib()
+        self.count = len(tensors)
+        if self.count == 0:
+            raise TuckerALSError(-1, "batched: no tensors")
+        dev = tensors[0].device
+        dims3, ranks3, a_off, u_off, g_off = [], [], [], [], []
+        ao = uo = go = 0
+        for A, rk in zip(tensors, ranks_list):
+            if A.dim() != 3 or A.dtype != torch.float32:
+                raise TuckerALSError(-1, "batched: order-3 float32 tensors only")
+            dims3 += list(A.shape)
+            ranks3 += list(rk)
+            a_off.append(ao)
+            ao += A.numel()
+            for n in range(3):
+                u_off.append(uo)
+                uo += A.shape[n] * rk[n]
+            g_off.append(go)
+            go += rk[0] * rk[1] * rk[2]
+        self.dims3, self.ranks3 = dims3, ranks3
+        self.a_off, self.u_off, self.g_off = a_off, u_off, g_off
+        self.A = torch.cat([t.reshape(-1) for t in tensors]).contiguous()
+        self.U = torch.empty(uo, dtype=torch.float32, device=dev)
+        self.G = torch.empty(go, dtype=torch.float32, device=dev)
+        self._d3, self._r3 = L.i64arr(dims3), L.i32arr(ranks3)
+        self._ao, self._uo, self._go = L.i64arr(a_off), L.i64arr(u_off), L.i64arr(g_off)
+        need = lib.als_sthosvd_batched_workspace_bytes(self.count, self._d3, self._r3)
+        if need == 0:
+            raise TuckerALSError(-1, "als_sthosvd_batched_workspace_bytes")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.iters = (ctypes.c_int32 * (3 * self.count))()
+        self.status = (ctypes.c_int32 * self.count)()
+
+    @property
+    def algorithmic_bytes_per_pass(self):
+        """Bytes of one read of every input tensor (FP32)."""
+        return 4 * self.A.numel()
+
+    def run(self, tol=1e-4, max_iters=50, seed=0, resid_mode="auto"):
+        lib = L.lib()
+        o, keep = _opts(tol, max_iters, seed, None, resid_mode)
+        rc = lib.als_sthosvd_batched(ctypes.c_void_p(self.A.data_ptr()), L.TK_F32, self.count,
+                                     self._d3, self._r3, self._ao, ctypes.byref(o),
+                                     ctypes.c_void_p(self.U.data_ptr()), self._uo,
+                                     ctypes.c_void_p(self.G.data_ptr()), self._go, self.iters,
+                                     self.status, ctypes.c_void_p(self.ws.data_ptr()),
+                                     self.ws.numel(), _stream(self.A.device))
+        del keep
+        sts = [self.status[t] for t in range(self.count)]
+        # a member's own failure (e.g. rank deficiency) is reported in its status;
+        # only call-level failures raise
+        if rc not in (0, 1) and rc not in sts:
+            L.check(rc, "als_sthosvd_batched")
+        return sts
+
+    def results(self):
+        out = []
+        for t in range(self.count):
+            d = self.dims3[3 * t:3 * t + 3]
+            rk = self.ranks3[3 * t:3 * t + 3]
+            Us = [self.U[self.u_off[3 * t + n]:self.u_off[3 * t + n] + d[n] * rk[n]]
+                  .view(d[n], rk[n]) for n in range(3)]
+            G = self.G[self.g_off[t]:self.g_off[t] + rk[0] * rk[1] * rk[2]].view(*rk)
+            out.append((G, Us, [self.iters[3 * t + n] for n in range(3)]))
+        return out
+
+
 def batched_sthosvd(tensors, ranks_list, tol=1e-4, max_iters=50, seed=0, resid_mode="auto"):
     """st-HOSVD-ALS of many small order-3 FP32 tensors in one batched call.
 
     Returns a list of (G, [U1, U2, U3], iters) and the per-tensor statuses."""
-    lib = L.lib()
-    count = len(tensors)
-    if count == 0:
+    if len(tensors) == 0:
         return [], []
-    dev = tensors[0].device
-    dims3, ranks3, a_off, u_off, g_off = [], [], [], [], []
-    ao = uo = go = 0
-    for A, rk in zip(tensors, ranks_list):
-        if A.dim() != 3 or A.dtype != torch.float32:
-            raise TuckerALSError(-1, "batched: order-3 float32 tensors only")
-        dims3 += list(A.shape)
-        ranks3 += list(rk)
-        a_off.append(ao)
-        ao += A.numel()
-        for n in range(3):
-            u_off.append(uo)
-            uo += A.shape[n] * rk[n]
-        g_off.append(go)
-        go += rk[0] * rk[1] * rk[2]
-    A_packed = torch.cat([t.reshape(-1) for t in tensors]).contiguous()
-    U_packed = torch.empty(uo, dtype=torch.float32, device=dev)
-    G_packed = torch.empty(go, dtype=torch.float32, device=dev)
-    d3, r3 = L.i64arr(dims3), L.i32arr(ranks3)
-    need = lib.als_sthosvd_batched_workspace_bytes(count, d3, r3)
-    if need == 0:
-        raise TuckerALSError(-1, "als_sthosvd_batched_workspace_bytes")
-    ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    iters = (ctypes.c_int32 * (3 * count))()
-    status = (ctypes.c_int32 * count)()
-    o, keep = _opts(tol, max_iters, seed, None, resid_mode)
-    rc = lib.als_sthosvd_batched(ctypes.c_void_p(A_packed.data_ptr()), L.TK_F32, count, d3, r3,
-                                 L.i64arr(a_off), ctypes.byref(o),
-                                 ctypes.c_void_p(U_packed.data_ptr()), L.i64arr(u_off),
-                                 ctypes.c_void_p(G_packed.data_ptr()), L.i64arr(g_off), iters,
-                                 status, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                                 _stream(dev))
-    sts = [status[t] for t in range(count)]
-    # a member's own failure (e.g. rank deficiency) is reported in its status;
-    # only call-level failures raise
-    if rc not in (0, 1) and rc not in sts:
-        L.check(rc, "als_sthosvd_batched")
-    out = []
-    for t in range(count):
-        d = dims3[3 * t:3 * t + 3]
-        rk = ranks3[3 * t:3 * t + 3]
-        Us = [U_packed[u_off[3 * t + n]:u_off[3 * t + n] + d[n] * rk[n]].view(d[n], rk[n])
-              for n in range(3)]
-        G = G_packed[g_off[t]:g_off[t] + rk[0] * rk[1] * rk[2]].view(*rk)
-        out.append((G, Us, [iters[3 * t + n] for n in range(3)]))
-    return out, sts
+    plan = BatchedPlan(tensors, ranks_list)
+    sts = plan.run(tol=tol, max_iters=max_iters, seed=seed, resid_mode=resid_mode)
+    return plan.results(), sts
 
 
 from .autograd import TuckerProject, TuckerReconstruct  # noqa: E402

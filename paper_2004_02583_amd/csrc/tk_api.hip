@@ -1314,6 +1314,47 @@ void tune_store(const std::string& key, int cfg) {
   }
 }
 
+// Instantiated graphs of the batched launch, by launch key (buffers, shapes,
+// options, tile shape); a small cache, oldest entry evicted.
+struct GraphCache {
+  std::mutex mu;
+  std::vector<std::pair<std::string, hipGraphExec_t>> entries;
+};
+GraphCache& graph_cache() {
+  static GraphCache* c = new GraphCache();   // kept until the process ends
+  return *c;
+}
+constexpr size_t GRAPH_CACHE_MAX = 8;
+
+hipGraphExec_t graph_lookup(const std::string& key) {
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  for (auto& e : c.entries)
+    if (e.first == key) return e.second;
+  return nullptr;
+}
+
+void graph_store(const std::string& key, hipGraphExec_t exec) {
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.entries.size() >= GRAPH_CACHE_MAX) {
+    (void)hipGraphExecDestroy(c.entries.front().second);
+    c.entries.erase(c.entries.begin());
+  }
+  c.entries.emplace_back(key, exec);
+}
+
+// FNV-1a over the descriptor table (part of the launch key).
+uint64_t desc_hash(const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
 // Times every tile shape on the batch itself (second of two runs each).
 int autotune_batched(const BatchLaunch& L, hipStream_t s, int* best_out) {
   hipEvent_t e0, e1;
@@ -1427,23 +1468,35 @@ int als_sthosvd_batched(const void* A_packed, int32_t a_dtype, int32_t count,
     if (rc) return rc;
     tune_store(key, cfg);
   }
-  // capture queue reset + persistent kernel in a graph on a private stream,
-  // replay it on the caller's stream
-  hipStream_t cs;
-  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-  if (ok) {
-    launch_batched(L, cfg, cs);
-    ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+  // the queue reset and the persistent kernel, captured once in a graph on a
+  // private stream and replayed on the caller's stream; the instantiated graph
+  // is kept for later calls with the same launch (buffers, shapes, options)
+  char gk[512];
+  snprintf(gk, sizeof gk, "%s/cfg%d/A%p/U%p/G%p/ws%p/n%d/t%.17g/m%d/r%d/s%llu/h%016llx",
+           key.c_str(), cfg, A_packed, U_packed, G_packed, ws, count, o.tol, o.max_iters,
+           o.resid_mode, (unsigned long long)o.seed,
+           (unsigned long long)desc_hash(hdesc.data(), batched_desc_bytes() * count));
+  hipGraphExec_t exec = graph_lookup(gk);
+  if (!exec) {
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      launch_batched(L, cfg, cs);
+      ok = hipStreamEndCapture(cs, &graph) == hipSuccess;
+    }
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (!ok) {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      return TK_ERR_HIP;
+    }
+    graph_store(gk, exec);
   }
-  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-  if (ok) ok = hipGraphLaunch(exec, s) == hipSuccess;
+  bool ok = hipGraphLaunch(exec, s) == hipSuccess;
   if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  (void)hipStreamDestroy(cs);
   if (!ok) return TK_ERR_HIP;
   std::vector<int32_t> hs(count), hi(3 * (size_t)count);
   HIPCHK(hipMemcpy(hs.data(), dstatus, 4 * (size_t)count, hipMemcpyDeviceToHost));

@@ -88,6 +88,43 @@ def test_batched_full_workload_sampled(gpu_lib):
         assert e_b < 2e-3
 
 
+def test_batched_plan_graph_replays(gpu_lib):
+    """BatchedPlan.run replays the HIP graph it captured on the first call: three calls with
+    eager device work between them give bitwise the results of the first, which equal a
+    fresh batched call's and stay within 1e-6 of single-tensor runs."""
+    tk = gpu_lib
+    items = _batch(40, 64, 10, k=7)
+    As = [torch.from_numpy(it["A"]).float().cuda() for it in items]
+    ranks = [it["ranks"] for it in items]
+    plan = tk.BatchedPlan(As, ranks)
+    flush("batched plan: first call (capture)")
+    st0 = plan.run(tol=1e-6, seed=2)
+    first = [(G.clone(), [u.clone() for u in Us], it) for G, Us, it in plan.results()]
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda")
+        junk = (junk * 2.0).sum()                     # eager work between the replays
+        plan.U.fill_(float("nan"))
+        plan.G.fill_(float("nan"))
+        torch.cuda.synchronize()
+        flush(f"batched plan: replay {rep}")
+        st = plan.run(tol=1e-6, seed=2)
+        assert st == st0
+        for (G0, U0, it0), (G1, U1, it1) in zip(first, plan.results()):
+            assert it0 == it1
+            assert torch.equal(G0, G1) and all(torch.equal(a, b) for a, b in zip(U0, U1))
+    fresh, sts = tk.batched_sthosvd(As, ranks, tol=1e-6, seed=2)
+    assert sts == st0
+    for (G0, U0, _), (G1, U1, _) in zip(first, fresh):
+        assert torch.equal(G0, G1) and all(torch.equal(a, b) for a, b in zip(U0, U1))
+    for t in range(0, 40, 7):
+        Ah = As[t].double().cpu().numpy()
+        G, Us, _ = first[t]
+        e_b = o.relerr(Ah, np64(G), [np64(u) for u in Us])
+        G1, U1, _ = tk.als_sthosvd(As[t], ranks[t], tol=1e-6, seed=2)
+        e_s = o.relerr(Ah, np64(G1), [np64(u) for u in U1])
+        assert abs(e_b - e_s) <= 1e-6 * max(1.0, e_s) + 1e-7, (t, e_b, e_s)
+
+
 # ------------------------------------------------------------ autograd
 
 def _loss(tk, A, Us):
