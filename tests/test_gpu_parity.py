@@ -435,6 +435,14 @@ KERNEL_CASES = [
     ((33, 392), 1, 20),         # Q == 1 (fibres are rows), one ragged fibre tile
     ((3, 1000, 8), 1, 5),       # R = 5, Q = 8, J = 24
     ((2, 1024, 40), 1, 48),     # I = 1024, R = 48, ragged fibre tiles
+    # modes of up to 224 rows with Q a multiple of 4, R up to 32, many tiles per workgroup
+    ((40, 200, 36), 1, 20),     # I = 200 (seven 32-row blocks), Q = 36 < 64: tiles straddle p
+    ((13, 64, 12), 1, 16),      # I = 64, one rank tile, ragged last tile
+    ((8, 100, 20), 1, 3),       # I = 100 (four blocks, the last ragged), R = 3
+    ((5, 224, 8), 1, 32),       # I = 224, R = 32 (largest), J = 40 < one tile
+    ((6, 1, 16), 1, 1),         # I = 1, R = 1
+    ((1, 150, 4), 1, 4),        # J = 4: one group of four fibres
+    ((40, 200, 1004), 1, 20),   # 627.5 tiles: both prefetch buffers cycle, ragged end
 ]
 
 
