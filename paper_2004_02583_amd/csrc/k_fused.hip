@@ -21,8 +21,12 @@
 //   L-update  16x16 output tiles (16 mode rows x 16 ranks), K = 64 fibres,
 //             dealt round-robin over the waves;
 //   Gram      wave w: V^T V over fibres 8w..8w+7, upper block triangle.
-// R is padded with zero columns to a multiple of 16.  Every reduction has a
-// fixed order (deterministic, no atomics).
+// R is padded with zero columns to a multiple of 16, except that with
+// 16 < R <= 20 the last four ranks take v_mfma_f32_4x4x1_16b_f32 instead
+// (RM variant, sweeps only): 16 blocks of 4 x 4 outputs, so the four ranks
+// cost a quarter of a padded 16-rank tile, on the waves that hold no other
+// R-update tile.  Every reduction has a fixed order
+// (deterministic, no atomics).
 #include "tk_kernels.h"
 
 namespace tk {
@@ -44,6 +48,12 @@ constexpr int NWG = 256;     // persistent workgroups (one per CU)
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// 16 independent 4 x 4 products, K = 1: block b = lane / 4; lane 4b + i holds
+// A_b[i], lane 4b + j holds B_b[j], and element i of lane 4b + j is
+// D_b[i][j] = A_b[i] B_b[j] + C_b[i][j].
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
 
 template <typename T> __device__ __forceinline__ float to_f(T x);
 template <> __device__ __forceinline__ float to_f<float>(float x) { return x; }
@@ -54,20 +64,26 @@ template <> __device__ __forceinline__ float to_f<bf16_t>(bf16_t x) { return bf1
 __host__ __device__ constexpr int rank_stride(int RP) { return (RP % 32 == 0) ? RP + 16 : RP; }
 
 struct Lds {
-  int xs, lq, lr, vf, total;  // offsets in floats
+  int xs, lq, lr, vf, vr, total;  // offsets in floats
 };
 
-__host__ __device__ inline Lds lds_layout(int I, int NR, int mode) {
+__host__ __device__ constexpr int round4(int x) { return (x + 3) & ~3; }
+
+// rm: room for the RM variant's final exchange of L-update sums ([4][64][4]).
+// Lq, V and those partials start on 16-byte boundaries (4-float reads).
+__host__ __device__ inline Lds lds_layout(int I, int NR, int mode, bool rm = false) {
   const int RP = 16 * NR;
   const int xrows = 16 * ((I + 15) / 16);
   const int RS = rank_stride(RP);
   Lds l;
   l.xs = 0;
-  l.lq = l.xs + (xrows + 1) * XLD;            // + spare row for the stash
+  l.lq = round4(l.xs + (xrows + 1) * XLD);    // + spare row for the stash
   l.lr = l.lq + (mode != 2 ? xrows * RS : 0);
-  l.vf = l.lr + (mode == 1 ? xrows * (RP + 1) : 0);
+  l.vf = round4(l.lr + (mode == 1 ? xrows * (RP + 1) : 0));
   // TTM keeps V transposed ([RP][TJ + 1]) for coalesced, conflict-free writes
   l.total = l.vf + (mode == 3 && RP * (TJ + 1) > TJ * RS ? RP * (TJ + 1) : TJ * RS);
+  l.vr = l.total;
+  if (rm) l.total = l.vr + 4 * TJ * 4;
   return l;
 }
 
@@ -151,16 +167,21 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
 
 // MODE 0: sweep; 1: sweep + explicit residual; 2: init (sketch, no Gram);
 // 3: TTM (R-update only, V written to Y).
-template <typename T, int NR, int MODE, int LAYOUT, int IC>
+template <typename T, int NR, int MODE, int LAYOUT, int IC, int RM>
 __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   extern __shared__ float smem[];
+  static_assert(!RM || (NR >= 2 && MODE <= 1), "the RM variant is a sweep with NR >= 2");
   constexpr int RP = 16 * NR;
   constexpr int RS = rank_stride(RP);        // Lq / Vf row stride
   constexpr int LRS = RP + 1;                // Lr row stride
   constexpr int NG = NR * (NR + 1) / 2;      // Gram output tiles
-  constexpr int U1 = (4 * NR + NW - 1) / NW; // R-update tiles per wave (max)
+  constexpr int NRF = RM ? NR - 1 : NR;      // rank tiles on the matrix cores
+  constexpr int U1 = (4 * NRF + NW - 1) / NW; // R-update tiles per wave (max)
   constexpr int RT = IC > 16 ? 2 : 1;        // L-update row tiles per wave (MT <= 8 RT)
-  constexpr int U2 = RT * NR;                // L-update tiles per wave
+  constexpr int U2 = RT * NRF;               // L-update tiles per wave
+  constexpr int C0 = 16 * NRF;               // first rank of the RM columns
+  constexpr int RMW = NW - 4 * NRF;          // RM: waves without an R-update tile
+  static_assert(!RM || RMW == 4, "the RM variant's partial buffer holds four waves' sums");
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
@@ -169,11 +190,12 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   const int lr = lane & 15, lk = lane >> 4;
   const int MT = (I + 15) / 16;              // 16-row tiles of the mode
   const int xrows = 16 * MT;
-  const Lds L = lds_layout(I, NR, MODE);
+  const Lds L = lds_layout(I, NR, MODE, RM != 0);
   float* Xs = smem + L.xs;
   float* Lq = smem + L.lq;
   float* Lr = smem + L.lr;
   float* Vf = smem + L.vf;
+  float* Vr = smem + L.vr;
 
   // ---- once per kernel: zero the X tile (rows >= I stay zero), load Lq/Lr
   for (int e = threadIdx.x; e < (xrows + 1) * XLD; e += NT) Xs[e] = 0.0f;
@@ -190,9 +212,12 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
       Lr[i * LRS + r] = (i < I && r < R) ? -a.Lr[i * R + r] : 0.0f;
     }
   }
+  // RM: V columns past C0 + 3 are never written (they stay zero)
+  if (RM)
+    for (int e = threadIdx.x; e < TJ * RS; e += NT) Vf[e] = 0.0f;
 
-  // R-update tiles: t = w + NW u -> (fibre block t / NR, rank tile t % NR)
-  const int cnt1 = 4 * NR > w ? (4 * NR - w + NW - 1) / NW : 0;
+  // R-update tiles: t = w + NW u -> (fibre block t / NRF, rank tile t % NRF)
+  const int cnt1 = 4 * NRF > w ? (4 * NRF - w + NW - 1) / NW : 0;
   f4 lacc[U2];
 #pragma unroll
   for (int u = 0; u < U2; ++u) lacc[u] = f4{0, 0, 0, 0};
@@ -205,6 +230,10 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
   double rsum = 0.0;
   const bool want_norm = MODE == 2 && a.norm2_parts != nullptr;
+  // RM: L-update of the last four ranks, wave w: mode rows 64 (w % 4) ..
+  // + 63 (block b: rows + 4b ..) over the fibre half w / 4 of every tile
+  f4 racc = f4{0.0f, 0.0f, 0.0f, 0.0f}, racc1 = racc;
+  const int rgrp = w & 3, rhalf = w >> 2;
 
   const T* X = (const T*)a.X;
   const int64_t ntiles = ceil_div(J, TJ);
@@ -235,7 +264,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
       for (int u = 0; u < U1; ++u) {
         if (u < cnt1) {
           const int t = w + NW * u;
-          const int fb = t / NR, n = t % NR;
+          const int fb = t / NRF, n = t % NRF;
           const float* xa = Xs + lk * XLD + 16 * fb + lr;
           const float* lb = Lq + lk * RS + 16 * n + lr;
           // Two register sets of stage operands in ping-pong: the reads of
@@ -283,6 +312,43 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
           }
         }
       }
+      if (RM && w >= NW - RMW) {
+        // the last four ranks on the waves without a 16-rank tile, wave w:
+        // fibres 16 w0 .. + 15 (w0 = w - NW + RMW).  Block b = 4c + g: fibres
+        // 16 w0 + 4g .. + 3 over the rows congruent to c mod 4, so lane l
+        // takes A = X[4s + l / 16][16 w0 + l % 16] and B = Lq[4s + l / 16][C0
+        // + l % 4]; the four row classes are added across lanes at the end.
+        // Two accumulators take alternate steps (independent products).
+        const int w0 = w - (NW - RMW);
+        f4 sv0 = f4{0.0f, 0.0f, 0.0f, 0.0f}, sv1 = sv0;
+        const float* xa = Xs + lk * XLD + 16 * w0 + lr;
+        const float* lb = Lq + lk * RS + C0 + (lane & 3);
+        // (xrows is a multiple of 16: a batch of four steps starting below
+        // it lies inside it, and its loads go out together)
+        for (int k = 0; k < xrows; k += 16) {
+          float xv[4], lv[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            xv[b] = xa[(k + 4 * b) * XLD];
+            lv[b] = lb[(k + 4 * b) * RS];
+          }
+          sv0 = mfma4(xv[0], lv[0], sv0);
+          sv1 = mfma4(xv[1], lv[1], sv1);
+          sv0 = mfma4(xv[2], lv[2], sv0);
+          sv1 = mfma4(xv[3], lv[3], sv1);
+        }
+        f4 sv = sv0 + sv1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          sv[q] += __shfl_xor(sv[q], 16, 64);
+          sv[q] += __shfl_xor(sv[q], 32, 64);
+        }
+        // element q of lane l < 16: fibre 16 w0 + 4 (l / 4) + q, rank C0 + l % 4
+        if (lane < 16) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Vf[(16 * w0 + 4 * (lane >> 2) + q) * RS + C0 + (lane & 3)] = sv[q];
+        }
+      }
     } else {
       // init: V = the Section 5 sketch rows of this tile
       for (int e = threadIdx.x; e < TJ * RP; e += NT) {
@@ -322,9 +388,9 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     // mode, duplicates are never stored) for every rank tile n; the RT * NR
     // independent accumulations are interleaved per K step.
     {
-      float vb[NR][16];
+      float vb[NRF][16];
 #pragma unroll
-      for (int n = 0; n < NR; ++n)
+      for (int n = 0; n < NRF; ++n)
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) vb[n][ks] = Vf[(4 * ks + lk) * RS + 16 * n + lr];
       const float* xr[RT];
@@ -344,10 +410,30 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-          for (int n = 0; n < NR; ++n)
-            lacc[rt * NR + n] = mfma16(ca[rt], vb[n][ks], lacc[rt * NR + n]);
+          for (int n = 0; n < NRF; ++n)
+            lacc[rt * NRF + n] = mfma16(ca[rt], vb[n][ks], lacc[rt * NRF + n]);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) ca[rt] = na[rt];
+      }
+      if (RM && 64 * rgrp < xrows) {
+        // A = X[64 g + lane][f] (rows past the tile read the spare row; their
+        // sums are never stored), B = V[f][C0 + lane % 4]
+        const float* xr = Xs + min(64 * rgrp + lane, xrows) * XLD + 32 * rhalf;
+        const float* vr = Vf + 32 * rhalf * RS + C0 + (lane & 3);
+#pragma unroll
+        for (int f0 = 0; f0 < 32; f0 += 8) {
+          float xv[8], vv[8];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            xv[b] = xr[f0 + b];
+            vv[b] = vr[(f0 + b) * RS];
+          }
+#pragma unroll
+          for (int b = 0; b < 8; b += 2) {
+            racc = mfma4(xv[b], vv[b], racc);
+            racc1 = mfma4(xv[b + 1], vv[b + 1], racc1);
+          }
+        }
       }
 
       if (MODE != 2) {
@@ -415,12 +501,27 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     const int m = w + NW * rt;
     if (m < MT) {
 #pragma unroll
-      for (int n = 0; n < NR; ++n) {
+      for (int n = 0; n < NRF; ++n) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int i = 16 * m + 4 * lk + q, r = 16 * n + lr;
-          if (i < I && r < R) lp[i * R + r] = lacc[rt * NR + n][q];
+          if (i < I && r < R) lp[i * R + r] = lacc[rt * NRF + n][q];
         }
+      }
+    }
+  }
+  if (RM) {
+    // fibre half 1 (waves 4..7) hands its sums to half 0 through LDS
+    racc += racc1;
+    if (rhalf == 1) *(f4*)(Vr + (rgrp * 64 + lane) * 4) = racc;
+    __syncthreads();
+    if (rhalf == 0) {
+      const f4 o = racc + *(const f4*)(Vr + (rgrp * 64 + lane) * 4);
+      const int r = C0 + (lane & 3);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 64 * rgrp + 4 * (lane >> 2) + q;
+        if (i < I && r < R) lp[i * R + r] = o[q];
       }
     }
   }
@@ -451,33 +552,50 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
 }
 
-template <typename T, int NR, int MODE, int IC>
+template <typename T, int NR, int MODE, int IC, int RM>
 void launch_ic(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
   if (a.v.Q != 1) {
-    (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC>,
+    (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC, RM>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, NR, MODE, 0, IC>), dim3(nwg), dim3(NT), bytes, s, a);
+    hipLaunchKernelGGL((k_fused<T, NR, MODE, 0, IC, RM>), dim3(nwg), dim3(NT), bytes, s, a);
   } else if constexpr (IC % 8 == 0) {      // Q == 1 slots are 64-row chunks
-    (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 1, IC>,
+    (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 1, IC, RM>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_fused<T, NR, MODE, 1, IC>), dim3(nwg), dim3(NT), bytes, s, a);
+    hipLaunchKernelGGL((k_fused<T, NR, MODE, 1, IC, RM>), dim3(nwg), dim3(NT), bytes, s, a);
   }
 }
 
 // Row-slot class: 8, 16, 26 or 32 slots per wave (I <= 64, 128, 208, 256;
 // the 26-slot class keeps two tiles of loads under the 63 outstanding loads
 // of a wave, and is taken only for Q > 1, whose slots are single rows).
-template <typename T, int NR, int MODE>
+template <typename T, int NR, int MODE, int RM = 0>
 void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
-  if (a.v.I <= 64) launch_ic<T, NR, MODE, 8>(a, nwg, bytes, s);
-  else if (a.v.I <= 128) launch_ic<T, NR, MODE, 16>(a, nwg, bytes, s);
-  else if (a.v.I <= 208 && a.v.Q != 1) launch_ic<T, NR, MODE, 26>(a, nwg, bytes, s);
-  else launch_ic<T, NR, MODE, 32>(a, nwg, bytes, s);
+  if (a.v.I <= 64) launch_ic<T, NR, MODE, 8, RM>(a, nwg, bytes, s);
+  else if (a.v.I <= 128) launch_ic<T, NR, MODE, 16, RM>(a, nwg, bytes, s);
+  else if (a.v.I <= 208 && a.v.Q != 1) launch_ic<T, NR, MODE, 26, RM>(a, nwg, bytes, s);
+  else launch_ic<T, NR, MODE, 32, RM>(a, nwg, bytes, s);
+}
+
+constexpr int LDS_MAX_BYTES = 160 * 1024;
+
+// The RM variant: a sweep with 16 < R <= 20, when its partial-sum buffer fits
+// (with a third rank tile the kernel would spill registers).
+bool use_rm(const FusedArgs& a, int NR, int mode) {
+  return NR == 2 && mode <= 1 && a.R - 16 * (NR - 1) <= 4 &&
+         (size_t)lds_layout((int)a.v.I, NR, mode, true).total * 4 <= (size_t)LDS_MAX_BYTES;
 }
 
 template <typename T, int NR>
 int launch_nr(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
-  const size_t bytes = (size_t)lds_layout((int)a.v.I, NR, mode).total * 4;
+  const bool rm = use_rm(a, NR, mode);
+  const size_t bytes = (size_t)lds_layout((int)a.v.I, NR, mode, rm).total * 4;
+  if constexpr (NR == 2) {
+    if (rm) {
+      if (mode == 0) launch_mode<T, NR, 0, 1>(a, nwg, bytes, s);
+      else launch_mode<T, NR, 1, 1>(a, nwg, bytes, s);
+      return nwg;
+    }
+  }
   if (mode == 0) launch_mode<T, NR, 0>(a, nwg, bytes, s);
   else if (mode == 1) launch_mode<T, NR, 1>(a, nwg, bytes, s);
   else if (mode == 2) launch_mode<T, NR, 2>(a, nwg, bytes, s);
@@ -496,8 +614,6 @@ int launch_t(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
 }
 
 }  // namespace
-
-constexpr int LDS_MAX_BYTES = 160 * 1024;
 
 bool fused_supported(int x_dtype, const View& v, int R, int resid_mode) {
   if (x_dtype != TK_F32 && x_dtype != TK_BF16) return false;
