@@ -23,7 +23,7 @@
 //   Gram      wave w: V^T V over fibres 8w..8w+7, upper block triangle.
 // R is padded with zero columns to a multiple of 16, except that with
 // 16 < R <= 20 the last four ranks take v_mfma_f32_4x4x1_16b_f32 instead
-// (RM variant, sweeps only): 16 blocks of 4 x 4 outputs, so the four ranks
+// (RM variant): 16 blocks of 4 x 4 outputs, so the four ranks
 // cost a quarter of a padded 16-rank tile, on the waves that hold no other
 // R-update tile.  Every reduction has a fixed order
 // (deterministic, no atomics).
@@ -170,7 +170,7 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
 template <typename T, int NR, int MODE, int LAYOUT, int IC, int RM>
 __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   extern __shared__ float smem[];
-  static_assert(!RM || (NR >= 2 && MODE <= 1), "the RM variant is a sweep with NR >= 2");
+  static_assert(!RM || NR >= 2, "the RM variant keeps at least one 16-rank tile");
   constexpr int RP = 16 * NR;
   constexpr int RS = rank_stride(RP);        // Lq / Vf row stride
   constexpr int LRS = RP + 1;                // Lr row stride
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   }
   // RM: V columns past C0 + 3 are never written (they stay zero)
   if (RM)
-    for (int e = threadIdx.x; e < TJ * RS; e += NT) Vf[e] = 0.0f;
+    for (int e = threadIdx.x; e < L.vr - L.vf; e += NT) Vf[e] = 0.0f;
 
   // R-update tiles: t = w + NW u -> (fibre block t / NRF, rank tile t % NRF)
   const int cnt1 = 4 * NRF > w ? (4 * NRF - w + NW - 1) / NW : 0;
@@ -346,7 +346,11 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
         // element q of lane l < 16: fibre 16 w0 + 4 (l / 4) + q, rank C0 + l % 4
         if (lane < 16) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) Vf[(16 * w0 + 4 * (lane >> 2) + q) * RS + C0 + (lane & 3)] = sv[q];
+          for (int q = 0; q < 4; ++q) {
+            const int f = 16 * w0 + 4 * (lane >> 2) + q, r = C0 + (lane & 3);
+            if (MODE == 3) Vf[r * (TJ + 1) + f] = sv[q];
+            else Vf[f * RS + r] = sv[q];
+          }
         }
       }
     } else {
@@ -578,10 +582,10 @@ void launch_mode(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
 
 constexpr int LDS_MAX_BYTES = 160 * 1024;
 
-// The RM variant: a sweep with 16 < R <= 20, when its partial-sum buffer fits
-// (with a third rank tile the kernel would spill registers).
+// The RM variant: 16 < R <= 20, when its exchange buffer fits (with a third
+// rank tile the kernel would spill registers).
 bool use_rm(const FusedArgs& a, int NR, int mode) {
-  return NR == 2 && mode <= 1 && a.R - 16 * (NR - 1) <= 4 &&
+  return NR == 2 && a.R - 16 * (NR - 1) <= 4 &&
          (size_t)lds_layout((int)a.v.I, NR, mode, true).total * 4 <= (size_t)LDS_MAX_BYTES;
 }
 
@@ -592,7 +596,9 @@ int launch_nr(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
   if constexpr (NR == 2) {
     if (rm) {
       if (mode == 0) launch_mode<T, NR, 0, 1>(a, nwg, bytes, s);
-      else launch_mode<T, NR, 1, 1>(a, nwg, bytes, s);
+      else if (mode == 1) launch_mode<T, NR, 1, 1>(a, nwg, bytes, s);
+      else if (mode == 2) launch_mode<T, NR, 2, 1>(a, nwg, bytes, s);
+      else launch_mode<T, NR, 3, 1>(a, nwg, bytes, s);
       return nwg;
     }
   }
