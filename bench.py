@@ -10,8 +10,17 @@ QRs, the TTM truncations) on the resident input.  `value` is the step's
 algorithmic HBM bytes (one read of the current tensor per pass plus the TTM
 writes) divided by the step time.  The `roofline` object times the fused ALS
 sweep kernel alone on mode 1 (6.4 GB per launch) with HIP events on the stream
-it is launched on.  `cpu_baseline` times the FP64 CPU oracle's literal ALS
+it is launched on.  Its arithmetic intensity (per fibre of I = 200 FP32
+values: 2IR flops for v_j, 2IR for the L_acc update, 2R^2 for G_V, i.e. 21
+flop/B at R = 20) lies above the FP32 matrix-core ridge (157.3 TFLOP/s over
+8 TB/s = 19.7 flop/B), so the roof that binds is the FP32 matrix core; the
+HBM figures are reported beside it.  `cpu_baseline` times the FP64 CPU oracle's literal ALS
 sweeps on a sample of the mode-1 unfolding.
+
+Beside the headline line, the same JSON carries BF16 storage on the same
+workload (time to tolerance against plain FP32), the 512-tensor batched
+workload, and the 1024^3 t-HOSVD-ALS workload in FP32 and BF16 storage
+(`large_*` keys; `--no-large` skips it, `--only-large` runs it alone).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -28,6 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix-core peak
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_fused_sweep_mode1_200x4_f32_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_02583_amd", "csrc", "k_fused.hip")
 DIMS = (200, 200, 200, 200)
@@ -66,21 +76,21 @@ def relerr_gpu(tk, A, G, Us):
     return e / torch.linalg.vector_norm(A.float()).item()
 
 
-def time_sweep_kernel(tk, A, Lq, launches=10):
-    """Average duration of the fused sweep kernel on mode 1, HIP events on
-    the stream the kernel is launched on (torch's current stream, which is
-    the stream handed to the library)."""
+def time_sweep_kernel(tk, A, Lq, launches=10, mode=0):
+    """Average duration of the fused sweep kernel on a mode (default the
+    first), HIP events on the stream the kernel is launched on (torch's
+    current stream, which is the stream handed to the library)."""
     import torch
-    ws = tk.step_workspace(A, 0, Lq.shape[1])
+    ws = tk.step_workspace(A, mode, Lq.shape[1])
     stream = torch.cuda.current_stream()
     for _ in range(2):
-        tk.als_sweep_kernel(A, 0, Lq, reduce=False, workspace=ws)
+        tk.als_sweep_kernel(A, mode, Lq, reduce=False, workspace=ws)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
     for _ in range(launches):
-        tk.als_sweep_kernel(A, 0, Lq, reduce=False, workspace=ws)
+        tk.als_sweep_kernel(A, mode, Lq, reduce=False, workspace=ws)
     stop.record(stream)
     stop.synchronize()
     return start.elapsed_time(stop) / launches
@@ -117,6 +127,51 @@ def copy_calibration(nbytes=1 << 30):
         dst.copy_(src)
     torch.cuda.synchronize()
     log(f"copy calibration: 3 copies of {nbytes} bytes")
+
+
+def bench_large(tk, steps, n=1024, core=64, rank=48, tol=1e-4):
+    """The 1024^3 workload: core 64^3 with entries N(0,1) 0.9^(i+j+k) times
+    orthonormal 1024x64 factors plus 1e-3 relative noise (seeded, generated
+    on the GPU); t-HOSVD-ALS to (48,48,48) with eta = 1e-4 in FP32 and in BF16
+    storage: time to tolerance, error against A, and the sweep kernel of each
+    mode with the returned factor (bytes = one read of the tensor)."""
+    import torch
+    from workloads import synth
+    A, _, _ = synth.tucker_lowrank_torch(2, (n,) * 3, (core,) * 3, 1e-3,
+                                         decay=synth.decay_geom((core,) * 3, 0.9),
+                                         device="cuda", out_dtype=torch.float32)
+    ranks = (rank,) * 3
+    out = {}
+    for name, X in (("f32", A), ("bf16", None)):
+        if X is None:
+            X = A.to(torch.bfloat16)
+        ws = torch.empty(tk.workspace_bytes("t", X.shape, X.dtype, ranks), dtype=torch.uint8,
+                         device="cuda")
+        G, Us, info = tk.als_thosvd(X, ranks, tol=tol, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            G, Us, info = tk.als_thosvd(X, ranks, tol=tol, workspace=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        e = relerr_gpu(tk, A, G, Us)
+        kms = [time_sweep_kernel(tk, X, Us[m].contiguous(), launches=5, mode=m) for m in range(3)]
+        nb = X.numel() * X.element_size()
+        log(f"1024^3 {name}: t-HOSVD-ALS {dt*1e3:.2f} ms iters={info['iters']} relerr={e:.4e} "
+            f"sweep kernels {['%.3f' % k for k in kms]} ms")
+        out[f"large_{name}_ms_per_thosvd"] = round(dt * 1e3, 3)
+        out[f"large_{name}_relerr"] = e
+        out[f"large_{name}_iters"] = info["iters"]
+        out[f"large_{name}_sweep_kernel_ms"] = [round(k, 4) for k in kms]
+        out[f"large_{name}_sweep_gbs"] = [round(nb / (k * 1e-3) / 1e9, 1) for k in kms]
+        del ws, G, Us
+        if name == "bf16":
+            del X
+    out["large_bf16_speedup_vs_f32"] = round(out["large_f32_ms_per_thosvd"] /
+                                             out["large_bf16_ms_per_thosvd"], 3)
+    out["large_workload"] = ("t-HOSVD-ALS, 1024^3, core 64^3 N(0,1)0.9^(i+j+k) x orthonormal "
+                             "1024x64 factors + 1e-3 relative noise, ranks (48,48,48), eta 1e-4")
+    return out
 
 
 def bench_batched(tk, steps, sample=64):
@@ -180,6 +235,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 t-HOSVD leg")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run the 1024^3 t-HOSVD leg alone (for profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
@@ -196,6 +254,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration()
+    if args.only_large:
+        print(json.dumps(bench_large(tk, max(1, min(args.steps, 3)))), flush=True)
+        return
     log("generating 200^4 FP32 workload on the GPU")
     w = synth.workload_4way_torch(DIMS, RANK, 1e-4, device=dev)
     A = w["A"]
@@ -228,6 +289,9 @@ def main():
     k_ms = time_sweep_kernel(tk, A, Lq)
     sweep_bytes = A.numel() * A.element_size()
     achieved = sweep_bytes / (k_ms * 1e-3) / 1e9
+    n_i, n_j, n_r = A.shape[0], A.numel() // A.shape[0], Lq.shape[1]
+    sweep_flops = float(n_j) * (4.0 * n_i * n_r + 2.0 * n_r * n_r)
+    tflops = sweep_flops / (k_ms * 1e-3) / 1e12
 
     extra = {}
     if not args.no_bf16:
@@ -255,6 +319,14 @@ def main():
         log("batched st-HOSVD-ALS (512 tensors)")
         extra.update(bench_batched(tk, args.steps))
 
+    if not args.no_large:
+        log("1024^3 t-HOSVD-ALS, FP32 and BF16 storage")
+        del G, Us
+        if not args.no_bf16:
+            del Gb, Ub
+        torch.cuda.empty_cache()
+        extra.update(bench_large(tk, max(1, min(args.steps, 3))))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -277,10 +349,13 @@ def main():
                                "x orthonormal 200x20 factors + 1e-4 relative noise",
                    "dims": list(DIMS), "ranks": list(ranks), "tol": TOL,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
+                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4),
                      "traffic": measured_traffic(), "kernel": "k_fused (ALS sweep, mode 1, FP32)",
-                     "kernel_ms": round(k_ms, 4), "bytes_per_launch": sweep_bytes},
+                     "kernel_ms": round(k_ms, 4), "flops_per_launch": sweep_flops,
+                     "bytes_per_launch": sweep_bytes, "hbm_gbs": round(achieved, 1),
+                     "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
         "iters": iters,
         "relerr": e32,
