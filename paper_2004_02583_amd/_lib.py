@@ -146,11 +146,13 @@ def _declare(lib):
 
 
 def load_library(path: str | None = None):
-    """Load libtucker_als.so (raises if it has not been built)."""
+    """Load libtucker_als.so (raises if it has not been built).  The
+    environment variable TUCKER_ALS_LIBRARY names another build of the same
+    library (the sanitizer build, for instance)."""
     global _lib
     if _lib is not None:
         return _lib
-    p = path or LIB_PATH
+    p = path or os.environ.get("TUCKER_ALS_LIBRARY") or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(
             f"{p} is missing: build it with `python -m paper_2004_02583_amd.build` "

@@ -116,6 +116,35 @@ def test_workspace_queries(lib):
         1, L.i64arr([20, 30, 40]), L.i32arr([40, 5, 6])) == 0
 
 
+def test_workspace_queries_many_shapes(lib):
+    """The host-side workspace carving over many shapes, orders, dtypes and
+    ranks (also the body of the sanitizer run): every query is positive,
+    t-HOSVD's never below the single-mode one, and growing a mode never
+    shrinks it."""
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        N = int(rng.integers(2, 7))
+        dims = [int(x) for x in rng.integers(1, 300, size=N)]
+        if rng.random() < 0.2:
+            dims[int(rng.integers(N))] = int(rng.integers(1000, 5000))
+        ranks = [int(rng.integers(1, min(d, 64) + 1)) for d in dims]
+        for dt in (L.TK_F64, L.TK_F32, L.TK_BF16):
+            st = lib.als_workspace_bytes(1, dt, N, L.i64arr(dims), L.i32arr(ranks))
+            t = lib.als_workspace_bytes(0, dt, N, L.i64arr(dims), L.i32arr(ranks))
+            # a Tucker core needs R_n <= prod_{k != n} R_k; other ranks are rejected
+            valid = all(ranks[n] <= np.prod([ranks[k] for k in range(N) if k != n])
+                        for n in range(N))
+            assert (st > 0) == valid and (t > 0) == valid, (dims, ranks, dt)
+            if not valid:
+                continue
+            grown = list(dims)
+            grown[0] += 17
+            assert lib.als_workspace_bytes(1, dt, N, L.i64arr(grown), L.i32arr(ranks)) >= st
+            rq = lib.tucker_reconstruct_workspace_bytes(dt, N, L.i32arr(ranks), L.i64arr(dims))
+            # (the reconstruction takes FP64 or FP32 cores and factors only)
+            assert (rq > 0) == (dt != L.TK_BF16), (dims, ranks, dt)
+
+
 def test_ttm_validation(lib):
     d = L.i64arr([4, 5, 6])
     assert lib.ttm(FAKE, 1, 3, d, 1, FAKE, 0, 3, 0, FAKE, 1, None) == -2   # M dtype

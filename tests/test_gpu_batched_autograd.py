@@ -216,3 +216,23 @@ def test_autograd_workload_fp32_vs_fp64_reference(gpu_lib):
     assert np.linalg.norm(ga - dA) <= 1e-4 * np.linalg.norm(dA)
     for g, want in zip(Ut, dUs):
         assert np.linalg.norm(np64(g.grad) - want) <= 1e-3 * np.linalg.norm(want)
+    # element by element under an FP32 accumulation bound: the same chain of
+    # products run on |A| and |U_n|, with E = A - A_hat bounded by |A| + |A_hat|
+    # terms, times gamma = 2 n u for n the summed lengths along the chain
+    # (project 3 x 256, reconstruct 3 x 32, their two adjoints, and the
+    # 32 x 32 contraction of dU_n)
+    a, u = np.abs(Ah), [np.abs(x) for x in Uh]
+    Gm = o.project(a, u)
+    Em = a + o.tucker_to_tensor(Gm, u)
+    dGm, dUrm = o.reconstruct_vjp(Gm, u, 2.0 * Em)
+    dApm, dUpm = o.project_vjp(a, u, dGm)
+    gamma = 2.0 * (2 * (3 * 256 + 3 * 32) + 32 * 32) * 2.0 ** -24
+    bound_a = gamma * (2.0 * Em + dApm)
+    ra = np.abs(ga - dA) / bound_a
+    flush(f"  dA: max |err| / bound = {ra.max():.3e}")
+    assert np.all(np.abs(ga - dA) <= bound_a)
+    for n, g in enumerate(Ut):
+        bound_u = gamma * (dUrm[n] + dUpm[n])
+        err = np.abs(np64(g.grad) - dUs[n])
+        flush(f"  dU_{n}: max |err| / bound = {(err / bound_u).max():.3e}")
+        assert np.all(err <= bound_u)
