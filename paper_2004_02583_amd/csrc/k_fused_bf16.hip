@@ -90,6 +90,8 @@ __host__ __device__ inline LdsB lds_b16(int I, int NR, int mode) {
 
 // Prefetch: slot k is row 8k + w (clamped) of the fibre pair j0 + 2 lane,
 // j0 + 2 lane + 1 (one dword; Q even keeps pairs inside one p and aligned).
+// Lanes past the end read the last pair and are zeroed in the stash, so a
+// tile wholly past the end is fetched (in bounds) and staged as zeros.
 template <int IC>
 __device__ __forceinline__ void prefetch(const uint32_t* __restrict__ X2, const View& v,
                                          int64_t j0, int lane, int w, uint32_t* pf, bool& ok) {
@@ -97,7 +99,7 @@ __device__ __forceinline__ void prefetch(const uint32_t* __restrict__ X2, const 
   const int I = (int)v.I;
   const int64_t j = j0 + 2 * lane;
   ok = j < J;
-  const uint32_t* b = X2 + (v.fibre_base(ok ? j : j0) >> 1);
+  const uint32_t* b = X2 + (v.fibre_base(ok ? j : J - 2) >> 1);
   const int64_t q2 = v.Q >> 1;
 #pragma unroll
   for (int k = 0; k < IC; ++k) {
@@ -414,6 +416,8 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   constexpr int XR = xrows_r(IC);
   constexpr int ICR = XR / NW;
   constexpr int STM = XR / 32;
+  // a second register buffer of tile loads, where the registers allow it
+  constexpr bool DB = !(MODE == 0 && NS == 3 && IC == 32);
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
@@ -456,33 +460,44 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int n = 0; n < NR; ++n) lacc[rt][n] = f4{0, 0, 0, 0};
-  f4 gacc[NG];
-  double gd[NG][4];
-#pragma unroll
-  for (int p = 0; p < NG; ++p) {
-    gacc[p] = f4{0, 0, 0, 0};
-    gd[p][0] = gd[p][1] = gd[p][2] = gd[p][3] = 0.0;
-  }
+  // G_V: unit w < 2 NG of wave w is block pair w / 2 = (gna, gnb), 32-fibre
+  // K step w % 2 of every tile
+  static_assert(2 * NG <= NW, "one G_V unit per wave");
+  const bool gown = w < 2 * NG;
+  int gna = 0, gnb = 0;
+  for (int x = 0, q = 0; x < NR; ++x)
+    for (int y = x; y < NR; ++y, ++q)
+      if (q == (w >> 1)) { gna = x; gnb = y; }
+  double gd[4] = {0.0, 0.0, 0.0, 0.0};
   double nsum = 0.0;
   const bool want_norm = MODE == 2 && a.norm2_parts != nullptr;
 
   const uint32_t* X2 = (const uint32_t*)a.X;
   const int64_t ntiles = ceil_div(J, TJ);
   const int nwg = gridDim.x;
-  uint32_t pf[ICR];
-  bool pf_ok = false;
+  // Two register buffers (DB) keep the loads of two tiles in flight: the
+  // buffer stashed for tile t + nwg then fetches tile t + 3 nwg.  Every
+  // prefetch and stash is unconditional (tiles past the end are fetched in
+  // bounds and staged as zeros, so they add nothing), and the loop has one
+  // shape, so the wait before a stash leaves the other buffer's loads in
+  // flight.  Without DB (register budget) one buffer fetches t + 2 nwg.
+  constexpr int NB = DB ? 2 : 1;
+  uint32_t pf0[ICR], pf1[ICR];
+  bool ok0 = false, ok1 = false;
   int64_t tile = blockIdx.x;
   int cur = 0;
   __syncthreads();
   if (tile < ntiles) {
-    prefetch<ICR>(X2, v, tile * TJ, lane, w, pf, pf_ok);
-    if (want_norm) stash<ICR, true>(v, lane, w, pf, pf_ok, XR, Xs32, nsum);
-    else stash<ICR, false>(v, lane, w, pf, pf_ok, XR, Xs32, nsum);
-    if (tile + nwg < ntiles) prefetch<ICR>(X2, v, (tile + nwg) * TJ, lane, w, pf, pf_ok);
+    prefetch<ICR>(X2, v, tile * TJ, lane, w, pf0, ok0);
+    if (want_norm) stash<ICR, true>(v, lane, w, pf0, ok0, XR, Xs32, nsum);
+    else stash<ICR, false>(v, lane, w, pf0, ok0, XR, Xs32, nsum);
+    prefetch<ICR>(X2, v, (tile + nwg) * TJ, lane, w, pf0, ok0);
+    if (DB) prefetch<ICR>(X2, v, (tile + 2 * nwg) * TJ, lane, w, pf1, ok1);
   }
   __syncthreads();
 
-  for (; tile < ntiles; tile += nwg, cur ^= 1) {
+  auto body = [&](const int64_t tile, uint32_t (&pf)[ICR], bool& pf_ok)
+                  __attribute__((always_inline)) {
     const int64_t j0 = tile * TJ;
     const __bf16* Xc = Xs + cur * xbuf;
 
@@ -545,12 +560,16 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
         Vt[(2 * RP + r) * VS + jl] = l;
       }
     }
-    if (tile + nwg < ntiles) {
+    {
+      // the next tile (zeros past the end; a duplicate norm term cannot
+      // arise: lanes past the end add nothing)
       uint32_t* Xn32 = Xs32 + (cur ^ 1) * (xbuf >> 1);
       if (want_norm) stash<ICR, true>(v, lane, w, pf, pf_ok, XR, Xn32, nsum);
       else stash<ICR, false>(v, lane, w, pf, pf_ok, XR, Xn32, nsum);
-      if (tile + 2 * nwg < ntiles)
-        prefetch<ICR>(X2, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
+      const int64_t ahead = tile + (NB + 1) * (int64_t)nwg;
+      // (past the end of the tensor by at most (NB + 1) nwg tiles: the
+      // clamp keeps the fibre index valid)
+      prefetch<ICR>(X2, v, (ahead < ntiles ? ahead : ntiles) * TJ, lane, w, pf, pf_ok);
     }
     __syncthreads();
 
@@ -586,43 +605,41 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
           }
         }
       }
-      if (MODE == 0) {
-        // G_V block pair p = (na, nb), K step ks: unit 4 p + ks goes to wave
-        // (4 p + ks) % 8; six split products each.
-        int p = 0;
+      if (MODE == 0 && gown) {
+        // this wave's G_V unit: the six split products above FP32 rounding
+        // (K step (w % 2) of the tile's fibres: two 32-fibre halves of the
+        // 128, i.e. fibres 64 (w % 2) .. + 63 in two 32-fibre steps)
+        f4 g = f4{0, 0, 0, 0};
 #pragma unroll
-        for (int na = 0; na < NR; ++na) {
-#pragma unroll
-          for (int nb = na; nb < NR; ++nb, ++p) {
-#pragma unroll
-            for (int ks = 0; ks < TJ / 32; ++ks) {
-              if (((4 * p + ks) & (NW - 1)) == w) {
-                const int ko = 32 * ks + 8 * lk;
-                const bf8 ah = *(const bf8*)(Vt + (0 * RP + 16 * na + lr) * VS + ko);
-                const bf8 am = *(const bf8*)(Vt + (1 * RP + 16 * na + lr) * VS + ko);
-                const bf8 al = *(const bf8*)(Vt + (2 * RP + 16 * na + lr) * VS + ko);
-                const bf8 bh = *(const bf8*)(Vt + (0 * RP + 16 * nb + lr) * VS + ko);
-                const bf8 bm = *(const bf8*)(Vt + (1 * RP + 16 * nb + lr) * VS + ko);
-                const bf8 bl = *(const bf8*)(Vt + (2 * RP + 16 * nb + lr) * VS + ko);
-                gacc[p] = mfma_bf16(ah, bh, gacc[p]);
-                gacc[p] = mfma_bf16(ah, bm, gacc[p]);
-                gacc[p] = mfma_bf16(am, bh, gacc[p]);
-                gacc[p] = mfma_bf16(ah, bl, gacc[p]);
-                gacc[p] = mfma_bf16(al, bh, gacc[p]);
-                gacc[p] = mfma_bf16(am, bm, gacc[p]);
-              }
-            }
-          }
+        for (int kk = 0; kk < TJ / 64; ++kk) {
+          const int ko = 64 * (w & 1) + 32 * kk + 8 * lk;
+          const bf8 ah = *(const bf8*)(Vt + (0 * RP + 16 * gna + lr) * VS + ko);
+          const bf8 am = *(const bf8*)(Vt + (1 * RP + 16 * gna + lr) * VS + ko);
+          const bf8 al = *(const bf8*)(Vt + (2 * RP + 16 * gna + lr) * VS + ko);
+          const bf8 bh = *(const bf8*)(Vt + (0 * RP + 16 * gnb + lr) * VS + ko);
+          const bf8 bm = *(const bf8*)(Vt + (1 * RP + 16 * gnb + lr) * VS + ko);
+          const bf8 bl = *(const bf8*)(Vt + (2 * RP + 16 * gnb + lr) * VS + ko);
+          g = mfma_bf16(ah, bh, g);
+          g = mfma_bf16(ah, bm, g);
+          g = mfma_bf16(am, bh, g);
+          g = mfma_bf16(ah, bl, g);
+          g = mfma_bf16(al, bh, g);
+          g = mfma_bf16(am, bm, g);
         }
 #pragma unroll
-        for (int q2 = 0; q2 < NG; ++q2) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) gd[q2][q] += (double)gacc[q2][q];
-          gacc[q2] = f4{0, 0, 0, 0};
-        }
+        for (int q = 0; q < 4; ++q) gd[q] += (double)g[q];
       }
     }
     __syncthreads();
+    cur ^= 1;
+  };
+  if (DB) {
+    for (; tile < ntiles; tile += 2 * nwg) {
+      body(tile, pf0, ok0);
+      body(tile + nwg, pf1, ok1);
+    }
+  } else {
+    for (; tile < ntiles; tile += nwg) body(tile, pf0, ok0);
   }
 
   // ---- per-workgroup outputs
@@ -649,19 +666,19 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
     }
   }
   if (MODE == 0) {
+    // this wave's G_V partial: its block pair (each diagonal block's upper
+    // triangle and its mirror, so it is exactly symmetric), zero elsewhere
     double* gp = a.gv_parts + (int64_t)(wg * NW + w) * R * R;
-    int p = 0;
+    for (int e = lane; e < R * R; e += 64) gp[e] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (gown) {
 #pragma unroll
-    for (int na = 0; na < NR; ++na) {
-#pragma unroll
-      for (int nb = na; nb < NR; ++nb, ++p) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = 16 * na + 4 * lk + q, col = 16 * nb + lr;
-          if (row < R && col < R && (na < nb || row <= col)) {
-            gp[row * R + col] = gd[p][q];
-            gp[col * R + row] = gd[p][q];
-          }
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * gna + 4 * lk + q, col = 16 * gnb + lr;
+        if (row < R && col < R && (gna < gnb || row <= col)) {
+          gp[row * R + col] = gd[q];
+          gp[col * R + row] = gd[q];
         }
       }
     }

@@ -236,3 +236,14 @@ def test_autograd_workload_fp32_vs_fp64_reference(gpu_lib):
         err = np.abs(np64(g.grad) - dUs[n])
         flush(f"  dU_{n}: max |err| / bound = {(err / bound_u).max():.3e}")
         assert np.all(err <= bound_u)
+    # that bound is rigorous but loose (absolute values compound along the
+    # chain); element by element against the rounding scale of the chain as
+    # well: sqrt(n) u (|g| + rms g) for the n summed terms, with a margin of 64
+    n_chain = 2 * (3 * 256 + 3 * 32) + 32 * 32
+    tau = 64.0 * np.sqrt(n_chain) * 2.0 ** -24
+    for name, got, want in [("dA", ga, dA)] + [(f"dU_{n}", np64(g.grad), dUs[n])
+                                               for n, g in enumerate(Ut)]:
+        scale = np.abs(want) + np.sqrt(np.mean(want ** 2))
+        r = np.abs(got - want) / scale
+        flush(f"  {name}: max |err| / (|g| + rms g) = {r.max():.3e} (tolerance {tau:.2e})")
+        assert np.all(r <= tau), name
