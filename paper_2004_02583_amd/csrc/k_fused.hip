@@ -27,6 +27,8 @@
 // cost a quarter of a padded 16-rank tile, on the waves that hold no other
 // R-update tile.  Every reduction has a fixed order
 // (deterministic, no atomics).
+#include <type_traits>
+
 #include "tk_kernels.h"
 
 namespace tk {
@@ -100,12 +102,37 @@ __host__ __device__ inline Lds lds_layout(int I, int NR, int mode, bool rm = fal
 // loads of the other.
 //  LAYOUT 1 (Q == 1): slot k = NC f + c is rows lane + 64c of fibre
 //          j0 + w + 8f (NC = IC/8 chunks of 64 rows per fibre, 8 fibres).
+//  LAYOUT 2 (FP32, Q a multiple of 4, 16-byte aligned tensor): 16-byte loads,
+//          a quarter of the load instructions of LAYOUT 0 (issuing them is
+//          what the slowest waves of a tile wait for): slot k holds rows
+//          32k + 4w + lane / 16 (clamped), fibres j0 + 4 (lane % 16) .. + 3,
+//          in pf[4k .. 4k + 3].
+template <int LAYOUT, int IC>
+__host__ __device__ constexpr int pf_slots() {
+  return LAYOUT == 2 ? 4 * ((NW * IC + 31) / 32) : IC;
+}
+
 template <typename T, int LAYOUT, int IC>
 __device__ __forceinline__ void prefetch(const T* __restrict__ X, const View& v, int64_t j0,
                                          int lane, int w, T* pf, bool& ok) {
   const int64_t J = v.J();
   const int I = (int)v.I;
-  if (LAYOUT == 0) {
+  if constexpr (LAYOUT == 2) {
+    constexpr int ICV = pf_slots<2, IC>() / 4;
+    const int64_t j = j0 + 4 * (lane & 15);
+    ok = j < J;
+    const float4* b = (const float4*)(X + v.fibre_base(ok ? j : J - 4));
+    const int64_t q4 = v.Q >> 2;
+#pragma unroll
+    for (int k = 0; k < ICV; ++k) {
+      const int ii = min(32 * k + 4 * w + (lane >> 4), I - 1);
+      const float4 x = b[(int64_t)ii * q4];
+      pf[4 * k + 0] = x.x;
+      pf[4 * k + 1] = x.y;
+      pf[4 * k + 2] = x.z;
+      pf[4 * k + 3] = x.w;
+    }
+  } else if (LAYOUT == 0) {
     const int64_t j = j0 + lane;
     ok = j < J;
     const T* b = X + v.fibre_base(ok ? j : J - 1);
@@ -138,7 +165,21 @@ __device__ __forceinline__ void stash(const View& v, int64_t j0, int lane, int w
   // (the squares go to four partial sums: one FP64 chain would wait out the
   // FMA latency at every element)
   double ns[4] = {0.0, 0.0, 0.0, 0.0};
-  if (LAYOUT == 0) {
+  if constexpr (LAYOUT == 2) {
+    constexpr int ICV = pf_slots<2, IC>() / 4;
+    const uint32_t keep = ok ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int k = 0; k < ICV; ++k) {
+      const int ii = 32 * k + 4 * w + (lane >> 4);
+      const int row = ii < I ? ii : xrows;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, pf[4 * k + e]) & keep);
+        Xs[row * XLD + 4 * (lane & 15) + e] = x;
+        if (NORM && ii < I) ns[e] += (double)x * (double)x;
+      }
+    }
+  } else if (LAYOUT == 0) {
     const uint32_t keep = ok ? 0xffffffffu : 0u;
 #pragma unroll
     for (int k = 0; k < IC; ++k) {
@@ -240,13 +281,14 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
   const int nwg = gridDim.x;
   // Two register buffers: while a tile is processed from LDS the next two
   // are in flight (two tiles of loads per wave, under the 63-load limit).
-  T pf0[IC], pf1[IC];
+  constexpr int PFN = pf_slots<LAYOUT, IC>();
+  T pf0[PFN], pf1[PFN];
   bool ok0 = false, ok1 = false;
   int64_t tile = blockIdx.x;
   prefetch<T, LAYOUT, IC>(X, v, tile * TJ, lane, w, pf0, ok0);
   prefetch<T, LAYOUT, IC>(X, v, (tile + nwg) * TJ, lane, w, pf1, ok1);
 
-  auto body = [&](const int64_t tile, T (&pf)[IC], bool& pf_ok) __attribute__((always_inline)) {
+  auto body = [&](const int64_t tile, T (&pf)[PFN], bool& pf_ok) __attribute__((always_inline)) {
     const int64_t j0 = tile * TJ;
     __syncthreads();
     if (MODE == 2 && want_norm) stash<T, LAYOUT, IC, true>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
@@ -369,7 +411,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     if (MODE == 3) {
       // fibre j of Y = B x_n U^T: Y[p, r, q] = V[j, r], coalesced along q
       float* Y = a.y;
-      if (LAYOUT == 0) {
+      if (LAYOUT != 1) {
         const int64_t j = j0 + lane;
         if (j < J) {
           const int64_t p = j / v.Q, q = j - p * v.Q;
@@ -558,6 +600,14 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
 
 template <typename T, int NR, int MODE, int IC, int RM>
 void launch_ic(const FusedArgs& a, int nwg, size_t bytes, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.v.Q % 4 == 0 && ((uintptr_t)a.X & 15) == 0) {
+      (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 2, IC, RM>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      hipLaunchKernelGGL((k_fused<T, NR, MODE, 2, IC, RM>), dim3(nwg), dim3(NT), bytes, s, a);
+      return;
+    }
+  }
   if (a.v.Q != 1) {
     (void)hipFuncSetAttribute((const void*)k_fused<T, NR, MODE, 0, IC, RM>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
