@@ -233,23 +233,32 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
                                ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
   const int spt = 2 * NCH;                   // steps per tile
   const int64_t total = my_tiles * spt;
-  // step s: tile blockIdx.x + (s / spt) gridDim.x, pass (s % spt) / NCH,
-  // chunk s % NCH
-  auto step_load = [&](int64_t s, uint4 (&rb)[SL]) __attribute__((always_inline)) {
-    const int64_t sc = s < total ? s : total - 1;
-    const int64_t tile = blockIdx.x + (sc / spt) * gridDim.x;
-    const int c = (int)(sc % spt) % NCH;
-    load_chunk<LAYOUT, NWK>(X16, v, tile * TJ, c, lane, w, rb);
+  // Step s works on tile blockIdx.x + (s / spt) gridDim.x, pass (s % spt) /
+  // NCH, chunk (s % spt) % NCH.  The positions (tile, step in the tile) of
+  // steps s, s + 1 and s + 2 are advanced by increments: no 64-bit division
+  // in the loop.
+  auto advance = [&](int64_t& t, int& st) __attribute__((always_inline)) {
+    if (++st == spt) {
+      st = 0;
+      t += gridDim.x;
+    }
   };
-  auto step_stash = [&](int64_t s, const uint4 (&rb)[SL]) __attribute__((always_inline)) {
-    const int64_t tile = blockIdx.x + (s / spt) * gridDim.x;
-    const int c = (int)(s % spt) % NCH;
-    stash_chunk<LAYOUT, NWK>(v, tile * TJ, c, lane, w, rb, Xs + (s & 1) * CE);
+  const int64_t t_last = blockIdx.x + (my_tiles - 1) * gridDim.x;
+  // (steps past the end load the last chunk again, so every load is
+  // unconditional)
+  auto step_load = [&](int64_t s, int64_t t, int st, uint4 (&rb)[SL]) __attribute__((always_inline)) {
+    const int64_t tt = s < total ? t : t_last;
+    const int sst = s < total ? st : spt - 1;
+    load_chunk<LAYOUT, NWK>(X16, v, tt * TJ, sst < NCH ? sst : sst - NCH, lane, w, rb);
+  };
+  auto step_stash = [&](int64_t s, int64_t t, int st, const uint4 (&rb)[SL])
+                        __attribute__((always_inline)) {
+    stash_chunk<LAYOUT, NWK>(v, t * TJ, st < NCH ? st : st - NCH, lane, w, rb,
+                             Xs + (s & 1) * CE);
   };
 
-  // the work of step s on its chunk buffer
-  auto step_work = [&](int64_t s) __attribute__((always_inline)) {
-    const int st = (int)(s % spt);
+  // the work of step s (position st in its tile) on its chunk buffer
+  auto step_work = [&](int64_t s, int st) __attribute__((always_inline)) {
     const __bf16* Xb = Xs + (s & 1) * CE;
     if (st < NCH) {
       // ---- pass 1: V += X_c^T Lq_c
@@ -371,18 +380,29 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 
   // ---- the step loop: one register buffer, two LDS chunk buffers
   uint4 rb0[SL];
+  int64_t t0 = blockIdx.x, t1 = t0, t2;
+  int st0 = 0, st1 = 0, st2;
+  advance(t1, st1);
+  t2 = t1;
+  st2 = st1;
+  advance(t2, st2);
   if (total > 0) {
-    step_load(0, rb0);
+    step_load(0, t0, st0, rb0);
     __syncthreads();
-    step_stash(0, rb0);
-    step_load(1, rb0);
+    step_stash(0, t0, st0, rb0);
+    step_load(1, t1, st1, rb0);
     __syncthreads();
   }
   for (int64_t s = 0; s < total; ++s) {
-    step_work(s);
-    if (s + 1 < total) step_stash(s + 1, rb0);
-    step_load(s + 2, rb0);
+    step_work(s, st0);
+    if (s + 1 < total) step_stash(s + 1, t1, st1, rb0);
+    step_load(s + 2, t2, st2, rb0);
     __syncthreads();
+    t0 = t1;
+    st0 = st1;
+    t1 = t2;
+    st1 = st2;
+    advance(t2, st2);
   }
 
   // ---- per-workgroup outputs
