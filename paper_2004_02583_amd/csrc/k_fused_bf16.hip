@@ -386,7 +386,10 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
 // the BF16 matrix cores (the six products h h, h m, m h, h l, l h, m m: the
 // three dropped ones are below FP32 rounding); and the tile is double
 // buffered in LDS, so the stash of the next tile overlaps this tile's
-// R-update.  Two barriers per tile.
+// R-update.  Two barriers per tile.  The sweep's L-update multiplies by the
+// two leading BF16 terms of V (16 significant bits: 2^-17 relative, far below
+// the tensor's own BF16 rounding); the Gram keeps the six exact split
+// products, which the trace residual needs.
 
 constexpr int XR_MAX_R = 224;
 
@@ -418,6 +421,10 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   constexpr int STM = XR / 32;
   // a second register buffer of tile loads, where the registers allow it
   constexpr bool DB = !(MODE == 0 && NS == 3 && IC == 32);
+  // BF16 terms of V in the L-update: the sweep takes V to 16 significant
+  // bits (h + m; 2^-17 relative, far below the tensor's own BF16 rounding),
+  // the init pass the exact three terms of the sketch
+  constexpr int NSV = MODE == 2 ? 3 : 2;
   const View v = a.v;
   const int I = (int)v.I, R = a.R;
   const int64_t J = v.J();
@@ -598,7 +605,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
 #pragma unroll
-          for (int s3 = 0; s3 < 3; ++s3) {
+          for (int s3 = 0; s3 < NSV; ++s3) {
             const bf8 bv = *(const bf8*)(Vt + (s3 * RP + 16 * n + lr) * VS + 32 * ks + 8 * lk);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) lacc[rt][n] = mfma_bf16(av[rt], bv, lacc[rt][n]);

@@ -6,8 +6,11 @@
 // G_V += v_j v_j^T, L_acc += a_j v_j^T.  The tensor is BF16 and the sweep's
 // Lq = L (L^T L)^{-1} arrives rounded to BF16 precision (the quantised L~ whose
 // Gram the trace residual uses), so the R-update is one BF16 product per term,
-// exact in FP32.  V is split exactly into three BF16 terms for the L-update and
-// the Gram (h + m + l = v), so those are exact products of the FP32 V.
+// exact in FP32.  V is split exactly into three BF16 terms (h + m + l = v): the
+// Gram takes the six split products above FP32 rounding (exact products of
+// the FP32 V, which the trace residual needs), the L-update the two leading
+// terms (V to 16 significant bits, 2^-17 relative, far below the tensor's own
+// BF16 rounding).
 //
 // Work layout: 256 persistent workgroups of NWK = 8 waves.  Lq^T stays in LDS for the
 // whole launch.  A tile of 64 fibres is streamed in chunks of 128 rows through
@@ -23,7 +26,7 @@
 //             v_mfma_f32_16x16x32_bf16, A = 16 fibres x 32 rows of the chunk,
 //             B = Lq^T (32 rows x 16 ranks);
 //   L-update  wave w: row tiles w + NWK i of every chunk, all rank tiles,
-//             K = the 64 fibres, three V splits;
+//             K = the 64 fibres, two V terms;
 //   Gram      wave w < NR (NR + 1) / 2: block pair w (na <= nb), the six split
 //             products above FP32 rounding.
 // LAYOUT 0 (Q > 1): the chunk is kept as [row][fibre]; the R-update gathers
@@ -344,6 +347,9 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) gd[q] += (double)g[q];
       }
+      // (V enters as its two leading BF16 terms, h + m: 2^-17 relative, far
+      // below the tensor's own BF16 rounding; the Gram above keeps all six
+      // products the trace residual needs)
       auto lupd = [&](f4 (&acc)[RTW][NR]) __attribute__((always_inline)) {
 #pragma unroll
         for (int ks = 0; ks < TJ / 32; ++ks) {
@@ -354,7 +360,7 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 #pragma unroll
           for (int n = 0; n < NR; ++n) {
 #pragma unroll
-            for (int s3 = 0; s3 < 3; ++s3) {
+            for (int s3 = 0; s3 < 2; ++s3) {
               const bf8 bv = *(const bf8*)(Vt + (s3 * RP + 16 * n + lr) * VS + 32 * ks + 8 * lk);
 #pragma unroll
               for (int i = 0; i < RTW; ++i) acc[i][n] = mfma_bf16(av[i], bv, acc[i][n]);
