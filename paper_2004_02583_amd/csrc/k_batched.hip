@@ -135,38 +135,46 @@ __device__ bool blk_qr(const double* L, int m, int r, double* Q1, double* Q, dou
   return false;
 }
 
-// One pass over the fibres of the view [P, I, Q] of X (FP32) in tiles of TJ:
-//  kind 0 (sweep): V = X^T W (W = L~ in LDS, FP32), G_V += V^T V (FP64 in
-//                  registers of thread < r(r+1)/2), Lacc += X V; with Lr
-//                  (L in LDS, FP32) also returns sum_j ||x_j - L v_j||^2
-//                  (the explicit residual, FP64 sums of FP32 differences);
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// D = A B + C with A 16x4 (lane l: row l%16, k l/16), B 4x16 (lane l: k l/16,
+// column l%16), D 16x16 (lane l, element q: row 4(l/16)+q, column l%16).
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One pass over the fibres of the view [P, I, Q] of X (FP32) in tiles of TJ,
+// every product on v_mfma_f32_16x16x4f32 (FP32 per tile, FP64 across tiles):
+//  kind 0 (sweep): V = X^T W (W = L~ in LDS, FP32), G_V += V^T V (written to
+//                  the LDS matrix GV, r x r), Lacc += X V; with Lr (L in LDS,
+//                  FP32) also returns sum_j ||x_j - L v_j||^2 (the explicit
+//                  residual, FP64 sums of the FP32 differences);
 //  kind 1 (init):  V = rows of the Section 5 sketch, Lacc += X V;
 //  kind 2 (TTM):   V = X^T W (W = U in LDS), written to Y[p][r][q];
 //                  returns sum V^2 (FP64) for the next mode's norm.
-// Lacc (FP64, m x r, global) is overwritten.
-// Gram pairs (a <= b) of thread t are t and t + NTH (r(r+1)/2 <= 136).
+// Lacc (FP64, m x r, global) is overwritten.  W and Lr are [16 ceil(I/16)][16]
+// with zeros past row I and rank r; rows I.. of the X tile are zeroed here.
 template <int NTH, int TJ>
 __device__ double blk_pass(int kind, const float* X, const View v, int r, const float* W,
-                           double* Lacc, double* gv, float* Y, uint64_t seed, int mode,
+                           double* Lacc, double* GV, float* Y, uint64_t seed, int mode,
                            float* Xt, float* Vt, int64_t* fb, double* red,
                            const float* Lr = nullptr) {
   constexpr int XS = TJ + 1;
+  constexpr int NW = NTH / 64;
+  constexpr int FT = TJ / 16;                  // fibre tiles of a tile
+  constexpr int MTW = (BI_MAX / 16 + NW - 1) / NW;   // L-update row tiles per wave
   const int I = (int)v.I;
+  const int I16 = 16 * ((I + 15) / 16);
+  const int MT = I16 / 16;
   const int64_t J = v.J();
-  // L-update accumulators: thread owns entries e = threadIdx.x + NTH k
-  constexpr int KMAX = BI_MAX * BR_MAX / NTH;
-  double lacc64[KMAX];
-  for (int k = 0; k < KMAX; ++k) lacc64[k] = 0.0;
-  const int np = r * (r + 1) / 2;
-  int ga[2] = {0, 0}, gb[2] = {0, 0};
-  for (int h = 0; h < 2; ++h) {
-    int rem = threadIdx.x + NTH * h, a = 0;
-    if (rem < np) {
-      while (rem >= r - a) { rem -= r - a; ++a; }
-      ga[h] = a;
-      gb[h] = a + rem;
-    }
-  }
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // the K padding of the products: rows I .. I16 - 1 of the tile stay zero
+  for (int e = threadIdx.x; e < (I16 - I) * XS; e += NTH) Xt[I * XS + e] = 0.0f;
+  double l64[MTW][4], g64[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < MTW; ++k) l64[k][0] = l64[k][1] = l64[k][2] = l64[k][3] = 0.0;
   double ssum = 0.0;
   for (int64_t j0 = 0; j0 < J; j0 += TJ) {
     if ((int)threadIdx.x < TJ) {
@@ -182,22 +190,25 @@ __device__ double blk_pass(int kind, const float* X, const View v, int r, const 
       const int64_t j = j0 + jj;
       Xt[ii * XS + jj] = (j < J) ? X[fb[jj] + (int64_t)ii * v.Q] : 0.0f;
     }
-    // V tile (TJ x r)
+    // V tile (TJ x 16, ranks past r zero)
     if (kind == 1) {
-      for (int e = threadIdx.x; e < TJ * r; e += NTH) {
-        const int jj = e / r, c = e % r;
+      for (int e = threadIdx.x; e < TJ * BR_MAX; e += NTH) {
+        const int jj = e / BR_MAX, c = e % BR_MAX;
         const int64_t j = j0 + jj;
-        Vt[jj * BR_MAX + c] =
-            (j < J) ? sketch_value(seed, ((uint64_t)mode << 48) + (uint64_t)(j * r + c)) : 0.0f;
+        Vt[e] = (j < J && c < r)
+                    ? sketch_value(seed, ((uint64_t)mode << 48) + (uint64_t)(j * r + c)) : 0.0f;
       }
     }
     __syncthreads();
     if (kind != 1) {
-      for (int e = threadIdx.x; e < TJ * r; e += NTH) {
-        const int jj = e % TJ, c = e / TJ;
-        float s = 0.0f;
-        for (int i = 0; i < I; ++i) s += W[i * BR_MAX + c] * Xt[i * XS + jj];
-        Vt[jj * BR_MAX + c] = s;
+      // V = X^T W: wave w takes the fibre tiles w, w + NW, .. (K = the rows)
+      for (int ft = w; ft < FT; ft += NW) {
+        f4 acc = f4{0, 0, 0, 0};
+        const float* xa = Xt + lk * XS + 16 * ft + lr;
+        const float* wb = W + lk * BR_MAX + lr;
+        for (int k4 = 0; k4 < I16; k4 += 4) acc = mfma16(xa[k4 * XS], wb[k4 * BR_MAX], acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Vt[(16 * ft + 4 * lk + q) * BR_MAX + lr] = acc[q];
       }
       __syncthreads();
     }
@@ -214,41 +225,71 @@ __device__ double blk_pass(int kind, const float* X, const View v, int r, const 
       }
     } else {
       if (kind == 0 && Lr) {
-        for (int e = threadIdx.x; e < I * TJ; e += NTH) {
-          const int i = e / TJ, jj = e % TJ;
-          if (j0 + jj < J) {
-            float d = Xt[i * XS + jj];
-            for (int c = 0; c < r; ++c) d -= Lr[i * BR_MAX + c] * Vt[jj * BR_MAX + c];
-            ssum += (double)d * (double)d;
-          }
+        // D = X - L V^T per (16-row tile m, fibre tile ft): C = X, A = -L
+        // (16 rows x 4 ranks), B = V^T (4 ranks x 16 fibres)
+        for (int t = w; t < MT * FT; t += NW) {
+          const int m = t / FT, ft = t - (t / FT) * FT;
+          f4 c;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) c[q] = Xt[(16 * m + 4 * lk + q) * XS + 16 * ft + lr];
+#pragma unroll
+          for (int k4 = 0; k4 < BR_MAX; k4 += 4)
+            c = mfma16(-Lr[(16 * m + lr) * BR_MAX + k4 + lk], Vt[(16 * ft + lr) * BR_MAX + k4 + lk], c);
+          const bool fin = j0 + 16 * ft + lr < J;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (fin && 16 * m + 4 * lk + q < I) ssum += (double)c[q] * (double)c[q];
         }
       }
-      if (kind == 0) {
-        for (int h = 0; h < 2; ++h) {
-          if ((int)threadIdx.x + NTH * h < np) {
-            double s = 0.0;
-            for (int jj = 0; jj < TJ; ++jj)
-              s += (double)(Vt[jj * BR_MAX + ga[h]] * Vt[jj * BR_MAX + gb[h]]);
-            gv[h] += s;
-          }
+      if (kind == 0 && w == 0) {
+        // G_V += V^T V (the A and B operands are the same reads)
+        f4 g = f4{0, 0, 0, 0};
+        for (int k4 = 0; k4 < TJ; k4 += 4) {
+          const float x = Vt[(k4 + lk) * BR_MAX + lr];
+          g = mfma16(x, x, g);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g64[q] += (double)g[q];
       }
-      for (int k = 0; k < KMAX; ++k) {
-        const int e = threadIdx.x + NTH * k;
-        if (e < I * r) {
-          const int i = e / r, c = e % r;
-          float s = 0.0f;
-          for (int jj = 0; jj < TJ; ++jj) s += Xt[i * XS + jj] * Vt[jj * BR_MAX + c];
-          lacc64[k] += (double)s;
+      // Lacc += X V: wave w takes the row tiles w + NW k (K = the fibres)
+#pragma unroll
+      for (int k = 0; k < MTW; ++k) {
+        const int m = w + NW * k;
+        if (m < MT) {
+          f4 acc = f4{0, 0, 0, 0};
+          const float* xa = Xt + (16 * m + lr) * XS + lk;
+          const float* vb = Vt + lk * BR_MAX + lr;
+#pragma unroll
+          for (int k4 = 0; k4 < TJ; k4 += 4) acc = mfma16(xa[k4], vb[k4 * BR_MAX], acc);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) l64[k][q] += (double)acc[q];
         }
       }
     }
     __syncthreads();
   }
   if (kind != 2) {
-    for (int k = 0; k < KMAX; ++k) {
-      const int e = threadIdx.x + NTH * k;
-      if (e < I * r) Lacc[e] = lacc64[k];
+#pragma unroll
+    for (int k = 0; k < MTW; ++k) {
+      const int m = w + NW * k;
+      if (m < MT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * m + 4 * lk + q;
+          if (i < I && lr < r) Lacc[i * r + lr] = l64[k][q];
+        }
+      }
+    }
+  }
+  if (kind == 0 && w == 0) {
+    // the lower triangle and its mirror: exactly symmetric
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 4 * lk + q;
+      if (row < r && lr <= row) {
+        GV[row * r + lr] = g64[q];
+        GV[lr * r + row] = g64[q];
+      }
     }
   }
   __syncthreads();
@@ -324,7 +365,8 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
       float* U = a.U + d.u_off[n];
       int it = 0;
       if (r == I) {
-        for (int e = threadIdx.x; e < I * I; e += NTH) Wl[(e / I) * BR_MAX + e % I] = (e / I == e % I);
+        for (int e = threadIdx.x; e < BI_MAX * BR_MAX; e += NTH)
+          Wl[e] = (e / BR_MAX < I && e / BR_MAX == e % BR_MAX) ? 1.0f : 0.0f;
         for (int e = threadIdx.x; e < I * I; e += NTH) U[e] = (e / I == e % I) ? 1.0f : 0.0f;
         __syncthreads();
       } else {
@@ -335,8 +377,7 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
         if (a.resid_mode == TK_RESID_AUTO && a.tol > 0.0)
           expl = 4.0 * 0x1p-24 * sqrt((double)(v.I + 64) / (double)v.J()) > 1e-4 * a.tol;
         // initial guess (Section 5): Y = B_(n) S, L0 = Q of its QR
-        double dummy[2] = {0.0, 0.0};
-        blk_pass<NTH, TJ>(1, B, v, r, nullptr, S.Lacc, dummy, nullptr, a.seed, n, Xt, Vt, fb,
+        blk_pass<NTH, TJ>(1, B, v, r, nullptr, S.Lacc, nullptr, nullptr, a.seed, n, Xt, Vt, fb,
                           red);
         if (blk_qr<NTH>(S.Lacc, I, r, S.Q1, S.L, G1, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
         double res_prev = 0.0;
@@ -345,9 +386,12 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
           blk_gram<NTH>(S.L, I, r, G1);
           if (blk_chol<NTH>(G1, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
           blk_rsolve<NTH>(S.L, I, r, G1, 1, S.Q1);
-          for (int e = threadIdx.x; e < I * r; e += NTH) {
-            Wl[(e / r) * BR_MAX + e % r] = (float)S.Q1[e];
-            if (expl) Ll[(e / r) * BR_MAX + e % r] = (float)S.L[e];
+          // (padded to [BI_MAX][16] with zeros: the K and N padding of the products)
+          for (int e = threadIdx.x; e < BI_MAX * BR_MAX; e += NTH) {
+            const int i = e / BR_MAX, c = e % BR_MAX;
+            const bool in = i < I && c < r;
+            Wl[e] = in ? (float)S.Q1[i * r + c] : 0.0f;
+            if (expl) Ll[e] = in ? (float)S.L[i * r + c] : 0.0f;
           }
           __syncthreads();
           for (int e = threadIdx.x; e < r * (r + 1) / 2; e += NTH) {
@@ -362,22 +406,8 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
           __syncthreads();
           if (blk_chol<NTH>(G2, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
           // sweep: V = B_(n)^T L~ (tiles), G_V, Lacc = B_(n) V
-          double gv[2] = {0.0, 0.0};
-          const double rsum = blk_pass<NTH, TJ>(0, B, v, r, Wl, S.Lacc, gv, nullptr, 0, 0, Xt,
+          const double rsum = blk_pass<NTH, TJ>(0, B, v, r, Wl, S.Lacc, GV, nullptr, 0, 0, Xt,
                                                 Vt, fb, red, expl ? Ll : nullptr);
-          {
-            const int np = r * (r + 1) / 2;
-            for (int h = 0; h < 2; ++h) {
-              if ((int)threadIdx.x + NTH * h < np) {
-                int aa = 0, rem = threadIdx.x + NTH * h;
-                while (rem >= r - aa) { rem -= r - aa; ++aa; }
-                const int bb = aa + rem;
-                GV[aa * r + bb] = gv[h];
-                GV[bb * r + aa] = gv[h];
-              }
-            }
-          }
-          __syncthreads();
           if (blk_chol<NTH>(GV, r, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
           blk_rsolve<NTH>(S.Lacc, I, r, GV, 1, S.Lnext);
           // captured energy tr(Gq^{-1} G_V) = ||Cq^{-1} D||_F^2 (Cq = G2, D = GV)
@@ -407,18 +437,17 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
         if (status < 0) break;
         // U = Q of the reduced QR of the returned L
         if (blk_qr<NTH>(S.L, I, r, S.Q1, S.Lnext, G1, &sh_bad)) { status = TK_ERR_RANK_DEFICIENT; break; }
-        for (int e = threadIdx.x; e < I * r; e += NTH) {
-          const float u = (float)S.Lnext[e];
-          U[e] = u;
-          Wl[(e / r) * BR_MAX + e % r] = u;
+        for (int e = threadIdx.x; e < I * r; e += NTH) U[e] = (float)S.Lnext[e];
+        for (int e = threadIdx.x; e < BI_MAX * BR_MAX; e += NTH) {
+          const int i = e / BR_MAX, c = e % BR_MAX;
+          Wl[e] = (i < I && c < r) ? (float)S.Lnext[i * r + c] : 0.0f;
         }
         __syncthreads();
       }
       if (threadIdx.x == 0) a.iters[3 * d.orig + n] = it;
       // B <- B x_n U^T (the last one lands in G)
       float* dst = (n == 2) ? a.G + d.g_off : ((n == 0) ? S.B0 : S.B1);
-      double dummy[2] = {0.0, 0.0};
-      normB2 = blk_pass<NTH, TJ>(2, B, v, r, Wl, nullptr, dummy, dst, 0, 0, Xt, Vt, fb, red);
+      normB2 = blk_pass<NTH, TJ>(2, B, v, r, Wl, nullptr, nullptr, dst, 0, 0, Xt, Vt, fb, red);
       cur[n] = r;
       B = dst;
     }
