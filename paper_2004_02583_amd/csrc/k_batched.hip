@@ -176,19 +176,43 @@ __device__ double blk_pass(int kind, const float* X, const View v, int r, const 
 #pragma unroll
   for (int k = 0; k < MTW; ++k) l64[k][0] = l64[k][1] = l64[k][2] = l64[k][3] = 0.0;
   double ssum = 0.0;
-  for (int64_t j0 = 0; j0 < J; j0 += TJ) {
-    if ((int)threadIdx.x < TJ) {
-      const int64_t j = j0 + threadIdx.x;
-      fb[threadIdx.x] = j < J ? v.fibre_base(j) : 0;
+  // The next tile's loads are in flight in registers while a tile is worked
+  // on: slot s of a thread is element e = threadIdx.x + NTH s of the tile
+  // (coalesced along q for Q > 1, along i for Q == 1); fb holds the fibre
+  // bases of two tiles (the current one's, then the next one's).
+  constexpr int NSLOT = BI_MAX * TJ / NTH;
+  float pre[NSLOT];
+  auto elem = [&](int e, int& ii, int& jj) __attribute__((always_inline)) {
+    if (v.Q == 1) { ii = e % I; jj = e / I; }
+    else { jj = e % TJ; ii = e / TJ; }
+  };
+  auto fetch = [&](int64_t j0, const int64_t* fbt) __attribute__((always_inline)) {
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      const int e = threadIdx.x + NTH * sl;
+      int ii = 0, jj = 0;
+      if (e < I * TJ) elem(e, ii, jj);
+      pre[sl] = (e < I * TJ && j0 + jj < J) ? X[fbt[jj] + (int64_t)ii * v.Q] : 0.0f;
     }
-    __syncthreads();
-    // X tile, coalesced along q (Q > 1) or along i (Q == 1)
-    for (int e = threadIdx.x; e < I * TJ; e += NTH) {
-      int ii, jj;
-      if (v.Q == 1) { ii = e % I; jj = e / I; }
-      else { jj = e % TJ; ii = e / TJ; }
-      const int64_t j = j0 + jj;
-      Xt[ii * XS + jj] = (j < J) ? X[fb[jj] + (int64_t)ii * v.Q] : 0.0f;
+  };
+  if ((int)threadIdx.x < TJ) fb[threadIdx.x] = (int64_t)threadIdx.x < J ? v.fibre_base(threadIdx.x) : 0;
+  __syncthreads();
+  fetch(0, fb);
+  int cur = 0;
+  for (int64_t j0 = 0; j0 < J; j0 += TJ, cur ^= 1) {
+    // X tile from the registers; the next tile's fibre bases
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      const int e = threadIdx.x + NTH * sl;
+      if (e < I * TJ) {
+        int ii, jj;
+        elem(e, ii, jj);
+        Xt[ii * XS + jj] = pre[sl];
+      }
+    }
+    if ((int)threadIdx.x < TJ) {
+      const int64_t j = j0 + TJ + threadIdx.x;
+      fb[(cur ^ 1) * TJ + threadIdx.x] = j < J ? v.fibre_base(j) : 0;
     }
     // V tile (TJ x 16, ranks past r zero)
     if (kind == 1) {
@@ -200,6 +224,7 @@ __device__ double blk_pass(int kind, const float* X, const View v, int r, const 
       }
     }
     __syncthreads();
+    if (j0 + TJ < J) fetch(j0 + TJ, fb + (cur ^ 1) * TJ);
     if (kind != 1) {
       // V = X^T W: wave w takes the fibre tiles w, w + NW, .. (K = the rows)
       for (int ft = w; ft < FT; ft += NW) {
@@ -329,7 +354,7 @@ __global__ void __launch_bounds__(NTH) k_batched(BatchArgs a) {
   __shared__ float Ll[BI_MAX * BR_MAX];   // L in FP32 for the explicit residual
   __shared__ double G1[GV_MAX], G2[GV_MAX], GV[GV_MAX];
   __shared__ double red[NTH];
-  __shared__ int64_t fb[TJ];
+  __shared__ int64_t fb[2 * TJ];
   __shared__ int sh_t, sh_bad;
   const Slot S = slot_of(a.scratch, a.slot_bytes, a.belems);
 
