@@ -5,7 +5,8 @@
 // adds up ||A||^2; the TTM variant writes v_j out), but a tile of 64 fibres no
 // longer fits LDS whole, so each tile is streamed in chunks of 128 rows:
 //   pass 1  V = sum over chunks of X_c^T Lq_c  (R-update; X_c and the matching
-//           rows of Lq staged in LDS, the next chunk prefetched in registers);
+//           rows of Lq staged in LDS, the next chunk of both prefetched in
+//           registers while the current one is worked on);
 //   Gram    G_V += V^T V from the finished V (FP32 per tile, FP64 across;
 //           wave w < NR (NR + 1) / 2 owns one 16 x 16 block pair);
 //   pass 2  L_acc[chunk rows] += X_c V  (L-update), the chunks read again:
@@ -54,8 +55,8 @@ __host__ __device__ inline LdsG lds_big(int NR, int mode) {
   const int RS = rank_stride(RP);
   LdsG l;
   l.xs = 0;
-  l.lq = l.xs + (CH + 1) * XLD;                     // + spare row
-  l.vf = l.lq + (mode != 2 ? CH * RS : 0);
+  l.lq = l.xs + CH * XLD;
+  l.vf = l.lq + (mode != 2 ? 2 * CH * RS : 0);      // two chunk buffers
   l.vp = l.vf + (mode == 3 ? RP * (TJ + 1) : TJ * RS);
   l.total = l.vp + (mode != 2 ? 2 * TJ * RS : 0);   // the two R-update halves
   return l;
@@ -90,8 +91,39 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ X, const View& 
   }
 }
 
-// Rows past I go to the spare row CH (no branches).  With NORM the squares of
-// the chunk's elements are added to nsum.
+// Copy of rows CH c .. CH c + 127 of Lq into an LDS buffer of CH x RS floats
+// by direct global -> LDS loads (no registers; the copy lands while the
+// previous chunk is worked on).  Instruction m of wave w fills the PER x 64
+// floats from PER * 64 (NW m + w) on, PER floats per lane; lane l's source is
+// that element's (row, rank), clamped into the factor, so rows past I and
+// ranks past R hold finite duplicates: the stash zeroes the matching X rows,
+// and ranks past R only reach outputs that are never written.  VEC moves 16
+// bytes per lane (Lq rows 16-byte aligned, ranks contiguous), else 4.
+template <int RS, bool VEC>
+__device__ __forceinline__ void issue_lq(const float* __restrict__ Lq, int I, int R, int64_t ldi,
+                                         int64_t ldo, int c, float* dst, int lane, int w) {
+  constexpr int PER = VEC ? 4 : 1;
+  static_assert((CH * RS) % (NT * PER) == 0, "the chunk splits evenly over the threads");
+  constexpr int NI = CH * RS / (NT * PER);
+#pragma unroll
+  for (int m = 0; m < NI; ++m) {
+    const int base = PER * 64 * (NW * m + w);
+    const int f = base + PER * lane;
+    const int r = f / RS, col = f - (f / RS) * RS;
+    const float* src = Lq + min(CH * c + r, I - 1) * ldi + min(col, R - PER) * ldo;
+    auto* d = (__attribute__((address_space(3))) void*)(dst + base);
+    if constexpr (VEC) __builtin_amdgcn_global_load_lds(src, d, 16, 0, 0);
+    else __builtin_amdgcn_global_load_lds(src, d, 4, 0, 0);
+  }
+}
+
+// s_waitcnt with vmcnt(0) (expcnt and lgkmcnt left at their maxima): this
+// wave's outstanding global loads, the direct-to-LDS copies included, are done.
+__device__ __forceinline__ void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Rows past I are written as zeros (no branches): the staged Lq rows there
+// are duplicates.  With NORM the squares of the chunk's elements are added to
+// nsum.
 template <typename T, int LAYOUT, bool NORM>
 __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, int lane, int w,
                                             const T* pf, bool ok, float* Xs, double& nsum) {
@@ -104,8 +136,8 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
     for (int k = 0; k < SL; ++k) {
       const int r = NW * k + w;
       const bool in = CH * c + r < I;
-      const float x = ok ? to_f<T>(pf[k]) : 0.0f;
-      Xs[(in ? r : CH) * XLD + lane] = x;
+      const float x = ok && in ? to_f<T>(pf[k]) : 0.0f;
+      Xs[r * XLD + lane] = x;
       if (NORM && in) ns[k & 3] += (double)x * (double)x;
     }
   } else {
@@ -116,8 +148,8 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
       const bool fok = j0 + w + NW * f < J;
       const int r = lane + 64 * h;
       const bool in = CH * c + r < I;
-      const float x = fok ? to_f<T>(pf[k]) : 0.0f;
-      Xs[(in ? r : CH) * XLD + w + NW * f] = x;
+      const float x = fok && in ? to_f<T>(pf[k]) : 0.0f;
+      Xs[r * XLD + w + NW * f] = x;
       if (NORM && in) ns[k & 3] += (double)x * (double)x;
     }
   }
@@ -145,7 +177,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_big(FusedArgs a) {
   float* Vp = smem + L.vp;
   const int64_t ldi = a.lq_ldi ? a.lq_ldi : R, ldo = a.lq_ldi ? a.lq_ldo : 1;
 
-  for (int e = threadIdx.x; e < (CH + 1) * XLD; e += NT) Xs[e] = 0.0f;
+  for (int e = threadIdx.x; e < CH * XLD; e += NT) Xs[e] = 0.0f;
 
   f4 lacc[NCHM][NR];
 #pragma unroll
@@ -165,6 +197,12 @@ __global__ void __launch_bounds__(NT, 1) k_fused_big(FusedArgs a) {
   const int64_t ntiles = ceil_div(J, TJ);
   T pf[SL];
   bool pf_ok = false;
+  const bool lq_vec = ldo == 1 && ldi % 4 == 0 && R % 4 == 0 && ((uintptr_t)a.Lq & 15) == 0;
+  auto lq_copy = [&](int c) __attribute__((always_inline)) {
+    float* dst = Lq + (c & 1) * CH * RS;
+    if (lq_vec) issue_lq<RS, true>(a.Lq, I, R, ldi, ldo, c, dst, lane, w);
+    else issue_lq<RS, false>(a.Lq, I, R, ldi, ldo, c, dst, lane, w);
+  };
 
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t j0 = tile * TJ;
@@ -176,23 +214,25 @@ __global__ void __launch_bounds__(NT, 1) k_fused_big(FusedArgs a) {
 #pragma unroll
       for (int k = 0; k < NR; ++k) vacc[k] = f4{0, 0, 0, 0};
       load_chunk<T, LAYOUT>(X, v, j0, 0, lane, w, pf, pf_ok);
+      lq_copy(0);
       for (int c = 0; c < NCH; ++c) {
+        // buffer (c + 1) & 1 was last read by chunk c - 1's products, which
+        // every wave has finished at the first barrier
         __syncthreads();
         stash_chunk<T, LAYOUT, false>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
-        for (int e = threadIdx.x; e < CH * RP; e += NT) {
-          const int r = e / RP, col = e - (e / RP) * RP;
-          const int i = CH * c + r;
-          Lq[r * RS + col] = (i < I && col < R) ? a.Lq[i * ldi + col * ldo] : 0.0f;
-        }
+        wait_vm0();
         __syncthreads();
-        if (c + 1 < NCH) load_chunk<T, LAYOUT>(X, v, j0, c + 1, lane, w, pf, pf_ok);
+        if (c + 1 < NCH) {
+          load_chunk<T, LAYOUT>(X, v, j0, c + 1, lane, w, pf, pf_ok);
+          lq_copy(c + 1);
+        }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           const int u = w + NW * k;
           const int h = u & 1, t = u >> 1;
           const int fb = t / NR, n = t % NR;
           const float* xa = Xs + (64 * h + lk) * XLD + 16 * fb + lr;
-          const float* lb = Lq + (64 * h + lk) * RS + 16 * n + lr;
+          const float* lb = Lq + (c & 1) * CH * RS + (64 * h + lk) * RS + 16 * n + lr;
           f4 acc = vacc[k];
 #pragma unroll
           for (int ks = 0; ks < 16; ++ks) acc = mfma16(xa[4 * ks * XLD], lb[4 * ks * RS], acc);
