@@ -270,26 +270,27 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) vacc[u] = f4{0, 0, 0, 0};
       }
+      // (the wave's tiles t = w + NWK u share the fibre block w % 4; the
+      // operands of the next 32-row block are read while this one's products
+      // run)
+      static_assert(NWK % 4 == 0, "a wave's R-update tiles share one fibre block");
+      const int fbw = 16 * (w & 3) + lr;
+      bf8 av[2], bv[2][NU];
+      auto rread = [&](int kb, int sl) __attribute__((always_inline)) {
+        const int row0 = 32 * kb + 8 * lk;
+        av[sl] = rupd_a<LAYOUT>(Xb, row0, fbw);
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+          if (u < nu)
+            bv[sl][u] = *(const bf8*)(Lq + (16 * ((w + NWK * u) >> 2) + lr) * LS + CH * c + row0);
+      };
+      rread(0, 0);
 #pragma unroll
       for (int kb = 0; kb < CH / 32; ++kb) {
-        const int row0 = 32 * kb + 8 * lk;
-        int fbp = -1;
-        bf8 av;
+        if (kb + 1 < CH / 32) rread(kb + 1, (kb + 1) & 1);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          if (u < nu) {
-            const int t = w + NWK * u;
-            const int fb = t & 3, n = t >> 2;
-            if (fb != fbp) {
-              av = rupd_a<LAYOUT>(Xb, row0, 16 * fb + lr);
-              fbp = fb;
-            }
-            const bf8 bv = *(const bf8*)(Lq + (16 * n + lr) * LS + CH * c + row0);
-            vacc[u] = mfma_bf16(av, bv, vacc[u]);
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        }
-        // (one 32-row block's operand reads at a time)
+        for (int u = 0; u < NU; ++u)
+          if (u < nu) vacc[u] = mfma_bf16(av[kb & 1], bv[kb & 1][u], vacc[u]);
         __builtin_amdgcn_sched_barrier(0);
       }
       if (c == NCH - 1) {
