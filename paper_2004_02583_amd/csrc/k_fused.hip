@@ -697,7 +697,7 @@ int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s) {
   int nwg = fused_workgroups(a.v);
   if (nwg > nwg_max / NW) nwg = nwg_max / NW;
   const int mode = a.y ? 3 : a.sketch ? 2 : (a.Lr ? 1 : 0);
-  if (fused_bf16_big_supported(a, mode)) return launch_fused_bf16_big(a, nwg_max, s);
+  if (fused_bf16_big_supported(a, mode)) return launch_fused_bf16_big(a, mode, nwg_max, s);
   if (fused_big_shape(a.x_dtype, a.v, a.R, mode)) return launch_fused_big(a, mode, nwg_max, s);
   if (fused_bf16_supported(a, mode)) return launch_fused_bf16(a, mode, nwg_max, s);
   if (a.x_dtype == TK_F32) return launch_t<float>(a, mode, nwg, s);

@@ -1,5 +1,6 @@
 // Fused ALS sweep for BF16 storage and large modes (256 < I_n <= 1024, R <= 48)
-// on the gfx950 BF16 matrix cores.
+// on the gfx950 BF16 matrix cores, and the initial sketch pass of the same
+// shapes (MODE 2).
 //
 // The products are those of the other sweep kernels (one HBM read of every
 // fibre a_j per sweep, row-wise rule of Section 3): v_j = Lq^T a_j,
@@ -11,6 +12,14 @@
 // the FP32 V, which the trace residual needs), the L-update the two leading
 // terms (V to 16 significant bits, 2^-17 relative, far below the tensor's own
 // BF16 rounding).
+//
+// The sketch pass (Section 5 initial guess): L_acc = B_(n) S for the sketch S
+// whose rows are generated in the kernel, with ||B||^2 from the staged values.
+// It is pass 2 alone; the sketch values are 24-bit multiples of 2^-24, so
+// their three BF16 terms are exact and the L-update takes all three (the
+// product is that of the FP32 sketch, up to FP32 accumulation).  The next
+// tile's sketch rows are split into the other of two V buffers during the
+// last step of a tile.
 //
 // Work layout: 256 persistent workgroups of NWK = 8 waves.  Lq^T stays in LDS for the
 // whole launch.  A tile of 64 fibres is streamed in chunks of 128 rows through
@@ -80,14 +89,16 @@ struct LdsBB {
   int lq, xs, vt, total;  // byte offsets
 };
 
-__host__ __device__ inline LdsBB lds_bb(int I, int NR, int LAYOUT) {
+// MODE 0: Lq^T, two chunk buffers, the three V^T splits; MODE 2: two chunk
+// buffers and two sets of V^T splits (this tile's and the next one's).
+__host__ __device__ inline LdsBB lds_bb(int I, int NR, int LAYOUT, int MODE) {
   const int RP = 16 * NR;
   const int KP = CH * ((I + CH - 1) / CH);   // rows padded to whole chunks
   LdsBB l;
   l.lq = 0;
-  l.xs = l.lq + RP * (KP + 8) * 2;
+  l.xs = l.lq + (MODE == 0 ? RP * (KP + 8) * 2 : 0);
   l.vt = l.xs + 2 * (LAYOUT == 0 ? CH * RS0 : TJ * RS1) * 2;
-  l.total = l.vt + 3 * RP * VS * 2;
+  l.total = l.vt + (MODE == 0 ? 1 : 2) * 3 * RP * VS * 2;
   return l;
 }
 
@@ -124,9 +135,12 @@ __device__ __forceinline__ void load_chunk(const uint4* __restrict__ X16, const 
   }
 }
 
-template <int LAYOUT, int NWK>
+// With NORM the squares of the staged values (zeros outside the tensor) are
+// added to ns (four FP64 partial sums).
+template <int LAYOUT, int NWK, bool NORM>
 __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, int lane, int w,
-                                            const uint4 (&rb)[16 / NWK], __bf16* Xb) {
+                                            const uint4 (&rb)[16 / NWK], __bf16* Xb,
+                                            double (&ns)[4]) {
   constexpr int SL = 16 / NWK;
   const int64_t J = v.J();
   const int I = (int)v.I;
@@ -136,12 +150,23 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
     const uint32_t m = keep ? 0xffffffffu : 0u;
     return make_uint4(x.x & m, x.y & m, x.z & m, x.w & m);
   };
+  auto sq = [&](const uint4& x) __attribute__((always_inline)) {
+    const uint32_t d[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double lo = (double)__uint_as_float(d[e] << 16);
+      const double hi = (double)__uint_as_float(d[e] & 0xffff0000u);
+      ns[e] += lo * lo + hi * hi;
+    }
+  };
   if (LAYOUT == 0) {
     const bool fok = j0 + 8 * (lane & 7) < J;
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
       const int r = 8 * w + (lane >> 3) + 8 * NWK * k;
-      *(uint4*)(Xb + cidx<0>(r, 8 * (lane & 7))) = masked(rb[k], fok && CH * c + r < I);
+      const uint4 x = masked(rb[k], fok && CH * c + r < I);
+      *(uint4*)(Xb + cidx<0>(r, 8 * (lane & 7))) = x;
+      if (NORM) sq(x);
     }
   } else {
     const int r = 8 * (lane & 15);
@@ -149,7 +174,9 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
       const int f = 4 * w + (lane >> 4) + 4 * NWK * k;
-      *(uint4*)(Xb + cidx<1>(r, f)) = masked(rb[k], rok && j0 + f < J);
+      const uint4 x = masked(rb[k], rok && j0 + f < J);
+      *(uint4*)(Xb + cidx<1>(r, f)) = x;
+      if (NORM) sq(x);
     }
   }
 }
@@ -176,8 +203,9 @@ __device__ __forceinline__ bf8 lupd_a(const __bf16* Xb, int row, int f0) {
   return a;
 }
 
-template <int NR, int LAYOUT, int NWK>
+template <int NR, int LAYOUT, int NWK, int MODE>
 __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
+  static_assert(MODE == 0 || MODE == 2, "sweep or sketch pass");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int NT = 64 * NWK;
   constexpr int SL = 16 / NWK;               // 16-byte load slots per thread and chunk
@@ -195,13 +223,16 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
   const int NCH = (I + CH - 1) / CH;
   const int KP = CH * NCH;
   const int LS = KP + 8;                     // Lq^T row stride
-  const LdsBB L = lds_bb(I, NR, LAYOUT);
+  const LdsBB L = lds_bb(I, NR, LAYOUT, MODE);
   __bf16* Lq = (__bf16*)(smem + L.lq);       // [RP][LS]: Lq^T
   __bf16* Xs = (__bf16*)(smem + L.xs);       // two chunk buffers
-  __bf16* Vt = (__bf16*)(smem + L.vt);       // [3][RP][VS]: V^T splits
+  __bf16* Vt = (__bf16*)(smem + L.vt);       // [3][RP][VS]: V^T splits (MODE 2: two sets)
+  constexpr int NTERM = MODE == 2 ? 3 : 2;   // V terms in the L-update
+  const bool want_norm = MODE == 2 && a.norm2_parts != nullptr;
+  double ns[4] = {0.0, 0.0, 0.0, 0.0};
 
   // ---- once per kernel: Lq^T (rows past I and ranks past R zero)
-  {
+  if (MODE == 0) {
     const int64_t ldi = a.lq_ldi ? a.lq_ldi : R, ldo = a.lq_ldi ? a.lq_ldo : 1;
     for (int e = threadIdx.x; e < RP * KP; e += NT) {
       const int r = e / KP, i = e - r * KP;
@@ -234,10 +265,10 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
   const int64_t ntiles = ceil_div(J, TJ);
   const int64_t my_tiles = (int64_t)blockIdx.x < ntiles
                                ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-  const int spt = 2 * NCH;                   // steps per tile
+  const int spt = MODE == 0 ? 2 * NCH : NCH;   // steps per tile
   const int64_t total = my_tiles * spt;
   // Step s works on tile blockIdx.x + (s / spt) gridDim.x, pass (s % spt) /
-  // NCH, chunk (s % spt) % NCH.  The positions (tile, step in the tile) of
+  // NCH, chunk (s % spt) % NCH (MODE 2: pass 2, chunk s % spt).  The positions (tile, step in the tile) of
   // steps s, s + 1 and s + 2 are advanced by increments: no 64-bit division
   // in the loop.
   auto advance = [&](int64_t& t, int& st) __attribute__((always_inline)) {
@@ -256,14 +287,35 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
   };
   auto step_stash = [&](int64_t s, int64_t t, int st, const uint4 (&rb)[SL])
                         __attribute__((always_inline)) {
-    stash_chunk<LAYOUT, NWK>(v, t * TJ, st < NCH ? st : st - NCH, lane, w, rb,
-                             Xs + (s & 1) * CE);
+    if (MODE == 2 && want_norm)
+      stash_chunk<LAYOUT, NWK, true>(v, t * TJ, st, lane, w, rb, Xs + (s & 1) * CE, ns);
+    else
+      stash_chunk<LAYOUT, NWK, false>(v, t * TJ, st < NCH ? st : st - NCH, lane, w, rb,
+                                      Xs + (s & 1) * CE, ns);
+  };
+  // MODE 2: the three BF16 terms of the sketch rows of tile t (zero past J
+  // and R) into V^T split set `set`
+  auto sketch_tile = [&](int64_t t, int set) __attribute__((always_inline)) {
+    __bf16* Vd = Vt + set * 3 * RP * VS;
+    for (int e = threadIdx.x; e < RP * TJ; e += NT) {
+      const int r = e / TJ, jl = e - (e / TJ) * TJ;
+      const int64_t j = t * TJ + jl;
+      float x = 0.0f;
+      if (j < J && r < R) x = sketch_value(a.seed, ((uint64_t)a.mode << 48) + (uint64_t)(j * R + r));
+      __bf16 h, m, l;
+      split3(x, h, m, l);
+      Vd[(0 * RP + r) * VS + jl] = h;
+      Vd[(1 * RP + r) * VS + jl] = m;
+      Vd[(2 * RP + r) * VS + jl] = l;
+    }
   };
 
-  // the work of step s (position st in its tile) on its chunk buffer
-  auto step_work = [&](int64_t s, int st) __attribute__((always_inline)) {
+  // the work of step s (position st in its tile) on its chunk buffer; MODE 2
+  // reads the V^T split set vset
+  auto step_work = [&](int64_t s, int st, int vset) __attribute__((always_inline)) {
     const __bf16* Xb = Xs + (s & 1) * CE;
-    if (st < NCH) {
+    const __bf16* Vw = Vt + (MODE == 2 ? vset * 3 * RP * VS : 0);
+    if (MODE == 0 && st < NCH) {
       // ---- pass 1: V += X_c^T Lq_c
       const int c = st;
       if (c == 0) {
@@ -321,8 +373,8 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
       }
     } else {
       // ---- pass 2: L_acc[chunk rows] += X_c V (row tiles w + NWK i of the chunk)
-      const int c = st - NCH;
-      if (c == 0 && gown) {
+      const int c = MODE == 0 ? st - NCH : st;
+      if (MODE == 0 && c == 0 && gown) {
         // G_V block pair (gna, gnb) from the V splits: the six split products
         // above FP32 rounding, the operands read a few at a time
         const int ra = 16 * gna + lr, rb = 16 * gnb + lr;
@@ -348,9 +400,10 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) gd[q] += (double)g[q];
       }
-      // (V enters as its two leading BF16 terms, h + m: 2^-17 relative, far
-      // below the tensor's own BF16 rounding; the Gram above keeps all six
-      // products the trace residual needs)
+      // (in the sweep V enters as its two leading BF16 terms, h + m: 2^-17
+      // relative, far below the tensor's own BF16 rounding; the Gram above
+      // keeps all six products the trace residual needs.  The sketch takes
+      // its three exact terms.)
       auto lupd = [&](f4 (&acc)[RTW][NR]) __attribute__((always_inline)) {
 #pragma unroll
         for (int ks = 0; ks < TJ / 32; ++ks) {
@@ -361,8 +414,8 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 #pragma unroll
           for (int n = 0; n < NR; ++n) {
 #pragma unroll
-            for (int s3 = 0; s3 < 2; ++s3) {
-              const bf8 bv = *(const bf8*)(Vt + (s3 * RP + 16 * n + lr) * VS + 32 * ks + 8 * lk);
+            for (int s3 = 0; s3 < NTERM; ++s3) {
+              const bf8 bv = *(const bf8*)(Vw + (s3 * RP + 16 * n + lr) * VS + 32 * ks + 8 * lk);
 #pragma unroll
               for (int i = 0; i < RTW; ++i) acc[i][n] = mfma_bf16(av[i], bv, acc[i][n]);
               // (one operand read in flight at a time: the registers go to L_acc)
@@ -393,15 +446,23 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
   t2 = t1;
   st2 = st1;
   advance(t2, st2);
+  int vset = 0;                               // MODE 2: split set of tile t0
   if (total > 0) {
     step_load(0, t0, st0, rb0);
     __syncthreads();
+    if (MODE == 2) sketch_tile(t0, 0);
     step_stash(0, t0, st0, rb0);
     step_load(1, t1, st1, rb0);
     __syncthreads();
   }
   for (int64_t s = 0; s < total; ++s) {
-    step_work(s, st0);
+    step_work(s, st0, vset);
+    if (MODE == 2 && st0 == spt - 1) {
+      // the next tile's sketch rows into the other set (its previous tile
+      // finished with it before the last barrier)
+      vset ^= 1;
+      if (s + 1 < total) sketch_tile(t1, vset);
+    }
     if (s + 1 < total) step_stash(s + 1, t1, st1, rb0);
     step_load(s + 2, t2, st2, rb0);
     __syncthreads();
@@ -414,6 +475,13 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
 
   // ---- per-workgroup outputs
   const int wg = blockIdx.x;
+  if (want_norm) {
+    double nsum = (ns[0] + ns[1]) + (ns[2] + ns[3]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nsum += __shfl_xor(nsum, off, 64);
+    static_assert(NWK == FUSED_WAVES, "one norm partial per wave");
+    if (lane == 0) a.norm2_parts[wg * FUSED_WAVES + w] = nsum;
+  }
   float* lp = a.lacc_parts + (int64_t)wg * I * R;
 #pragma unroll
   for (int c = 0; c < NCHM; ++c) {
@@ -431,6 +499,7 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
       }
     }
   }
+  if (MODE == 2) return;
   // G_V partials, FUSED_WAVES slots per workgroup: wave w fills slots
   // w + NWK k, its block pair in the first (each diagonal block's upper triangle
   // and its mirror, so it is exactly symmetric), zero elsewhere
@@ -453,20 +522,25 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
   }
 }
 
-template <int NR, int LAYOUT>
+template <int NR, int LAYOUT, int MODE>
 void launch_bb(const FusedArgs& a, int nwg, hipStream_t s) {
   constexpr int NWK = 8;
-  const size_t bytes = (size_t)lds_bb((int)a.v.I, NR, LAYOUT).total;
-  (void)hipFuncSetAttribute((const void*)k_fused_bf16_big<NR, LAYOUT, NWK>,
+  const size_t bytes = (size_t)lds_bb((int)a.v.I, NR, LAYOUT, MODE).total;
+  (void)hipFuncSetAttribute((const void*)k_fused_bf16_big<NR, LAYOUT, NWK, MODE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  hipLaunchKernelGGL((k_fused_bf16_big<NR, LAYOUT, NWK>), dim3(nwg), dim3(64 * NWK), bytes, s,
-                     a);
+  hipLaunchKernelGGL((k_fused_bf16_big<NR, LAYOUT, NWK, MODE>), dim3(nwg), dim3(64 * NWK),
+                     bytes, s, a);
 }
 
 template <int NR>
-void launch_bb_nr(const FusedArgs& a, int nwg, hipStream_t s) {
-  if (a.v.Q == 1) launch_bb<NR, 1>(a, nwg, s);
-  else launch_bb<NR, 0>(a, nwg, s);
+void launch_bb_nr(const FusedArgs& a, int mode, int nwg, hipStream_t s) {
+  if (mode == 2) {
+    if (a.v.Q == 1) launch_bb<NR, 1, 2>(a, nwg, s);
+    else launch_bb<NR, 0, 2>(a, nwg, s);
+  } else {
+    if (a.v.Q == 1) launch_bb<NR, 1, 0>(a, nwg, s);
+    else launch_bb<NR, 0, 0>(a, nwg, s);
+  }
 }
 
 }  // namespace
@@ -475,7 +549,8 @@ constexpr int LDS_MAX_BYTES_BB = 160 * 1024;
 
 bool fused_bf16_big_supported(const FusedArgs& a, int mode) {
   const View& v = a.v;
-  if (a.x_dtype != TK_BF16 || mode != 0 || !a.lq_bf16) return false;
+  if (a.x_dtype != TK_BF16) return false;
+  if (!(mode == 0 && a.lq_bf16) && mode != 2) return false;
   if (v.I <= 256 || v.I > (int64_t)CH * NCHM || a.R < 1 || a.R > 48) return false;
   if ((uintptr_t)a.X & 15) return false;
   // LAYOUT 0 loads eight fibres of a row (Q a multiple of 8), LAYOUT 1 eight
@@ -483,17 +558,17 @@ bool fused_bf16_big_supported(const FusedArgs& a, int mode) {
   if (v.Q == 1 ? (v.I & 7) : (v.Q & 7)) return false;
   if (v.J() < 8) return false;
   const int NR = (a.R + 15) / 16;
-  return (size_t)lds_bb((int)v.I, NR, v.Q == 1 ? 1 : 0).total <= (size_t)LDS_MAX_BYTES_BB;
+  return (size_t)lds_bb((int)v.I, NR, v.Q == 1 ? 1 : 0, mode).total <= (size_t)LDS_MAX_BYTES_BB;
 }
 
-int launch_fused_bf16_big(const FusedArgs& a, int nwg_max, hipStream_t s) {
+int launch_fused_bf16_big(const FusedArgs& a, int mode, int nwg_max, hipStream_t s) {
   const int64_t ntiles = ceil_div(a.v.J(), TJ);
   int nwg = (int)(ntiles < NWG ? ntiles : NWG);
   if (nwg > nwg_max / FUSED_WAVES) nwg = nwg_max / FUSED_WAVES;
   switch ((a.R + 15) / 16) {
-    case 1: launch_bb_nr<1>(a, nwg, s); break;
-    case 2: launch_bb_nr<2>(a, nwg, s); break;
-    case 3: launch_bb_nr<3>(a, nwg, s); break;
+    case 1: launch_bb_nr<1>(a, mode, nwg, s); break;
+    case 2: launch_bb_nr<2>(a, mode, nwg, s); break;
+    case 3: launch_bb_nr<3>(a, mode, nwg, s); break;
   }
   return nwg;
 }

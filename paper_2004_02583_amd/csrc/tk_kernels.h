@@ -121,11 +121,11 @@ int launch_fused(const FusedArgs& a, int nwg_max, hipStream_t s);
 bool fused_bf16_supported(const FusedArgs& a, int mode);
 int launch_fused_bf16(const FusedArgs& a, int mode, int nwg_max, hipStream_t s);
 // BF16 storage, modes of 256 < I <= 1024 rows, R <= 48, sweep with
-// BF16-representable Lq: on the BF16 matrix cores, Lq resident in LDS, the
-// fibres streamed in chunks of rows; used by launch_fused when it takes the
-// shape.
+// BF16-representable Lq (Lq resident in LDS) or the initial sketch pass: on
+// the BF16 matrix cores, the fibres streamed in chunks of rows; used by
+// launch_fused when it takes the shape.
 bool fused_bf16_big_supported(const FusedArgs& a, int mode);
-int launch_fused_bf16_big(const FusedArgs& a, int nwg_max, hipStream_t s);
+int launch_fused_bf16_big(const FusedArgs& a, int mode, int nwg_max, hipStream_t s);
 // Rounds n FP32 values to BF16 precision in place (round to nearest even).
 void launch_round_bf16(float* x, int64_t n, hipStream_t s);
 // Modes of 256 < I <= 1024 rows (R <= 48; sweep, init, TTM), streamed in

@@ -139,6 +139,42 @@ def test_init_step_parity(gpu_lib, dims, mode, R, dt):
     np.testing.assert_allclose(Q, Qo, atol=1e-10)
 
 
+# modes of 256 < I <= 1024 rows: the chunked sketch kernels (BF16 storage on
+# the BF16 matrix cores when Q, or I when Q == 1, is a multiple of 8)
+INIT_LARGE_CASES = [
+    ((16, 520, 24), 1, 48),     # R = 48, five chunks (the last ragged), Q = 24
+    ((33, 392), 1, 20),         # Q == 1 (fibres are rows), one ragged fibre tile
+    ((3, 1000, 8), 1, 5),       # R = 5, Q = 8, J = 24
+    ((2, 1024, 40), 1, 48),     # I = 1024, ragged fibre tiles, several tiles per sketch set
+    ((300, 20, 40), 0, 12),     # P == 1, I = 300 (last chunk 44 rows)
+    ((7, 600, 33), 1, 40),      # Q = 33: BF16 widened to FP32 on the FP32 matrix core
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("dims,mode,R", INIT_LARGE_CASES)
+def test_init_step_parity_large(gpu_lib, dims, mode, R, dt):
+    """Initial sketch pass (Section 5) on large modes: Y = A_(n) S and ||A||^2
+    against FP64 on the same stored values (FP32 accumulation of up to J
+    products per entry), and L_0 the QR of Y."""
+    tk = gpu_lib
+    flush(f"init large {dims} mode={mode} R={R} {dt}")
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal(dims)
+    seed = 99
+    Y, L0, n2 = tk.als_init_step(to_gpu(A, dt), mode, R, seed=seed)
+    Ah = held(A, dt)
+    An = o.unfold(Ah, mode)
+    S = o.init_sketch(seed, mode, An.shape[1], R)
+    want = An @ S
+    assert np.max(np.abs(np64(Y) - want)) <= 1e-5 * np.abs(want).max()
+    assert abs(n2 - o.frob(Ah) ** 2) <= 1e-12 * o.frob(Ah) ** 2
+    Q = np64(L0)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(R), atol=1e-12)
+    Qo, _ = o.qr_signfix(np64(Y))
+    np.testing.assert_allclose(Q, Qo, atol=1e-10)
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("resid", ["trace", "explicit"])
 @pytest.mark.parametrize("dims,mode,R", STEP_CASES)
