@@ -1,6 +1,6 @@
-// One-workgroup FP64 small linear algebra between two fibre passes of the
-// ALS mode solve (Algorithm 3.3), so that a sweep costs one fused pass, one
-// reduction and one launch of this kernel:
+// FP64 small linear algebra between two fibre passes of the ALS mode solve
+// (Algorithm 3.3), so that a sweep costs one fused pass, one reduction and one
+// launch of this kernel:
 //   SOLVE  L_{k+1} = L_acc (R_k^T R_k)^{-1} with G_V = R_k^T R_k, and the
 //          residual from the trace identity ||B||^2 - tr(Gq^{-1} G_V)
 //          (or the explicit sum);
@@ -21,7 +21,17 @@
 // tiles in flight; each pass multiplies the tile by an r x r LDS matrix on
 // the FP64 matrix cores and accumulates the Gram of the result, so that a
 // sweep reads L_acc once and L_{k+1} once.  All sums have a fixed order.
+// With a partial buffer and more than one row tile the kernel runs as a
+// cooperative grid of G workgroups: workgroup b streams a fixed contiguous
+// range of the row tiles (the same range in every pass, so it reads back only
+// rows it wrote), writes its Gram partial to the buffer, and after a grid
+// barrier every workgroup adds the G partials in workgroup order.  The r x r
+// work is repeated in every workgroup on identical values, so all of them
+// take the same decisions (the rank test included); workgroup 0 writes the
+// scalar and r x r outputs.
 #include <math.h>
+
+#include <hip/hip_cooperative_groups.h>
 
 #include "tk_kernels.h"
 
@@ -69,11 +79,11 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 
 // LDS row stride of the r x r matrices and the tiles (odd: the strided
 // column reads of the matrix-core operands spread over the banks).
-__device__ __forceinline__ int lds_ld(int r) { return (r & 1) ? r : r + 1; }
+__host__ __device__ inline int lds_ld(int r) { return (r & 1) ? r : r + 1; }
 
 // Rows per staged tile: a multiple of 16, at most NT EPT / r and 256, and
 // small enough for four r x r matrices and two tiles in POOL.
-__device__ __forceinline__ int tile_rows(int r) {
+__host__ __device__ inline int tile_rows(int r) {
   const int ld = lds_ld(r);
   int tr = ((NT * EPT) / r) & ~15;
   if (tr > 256) tr = 256;
@@ -86,11 +96,12 @@ struct Lay {
   ldsd *A, *B, *C, *M, *Ti, *To;   // contiguous in this order
 };
 
-__device__ __forceinline__ Lay make_lay(int r, ldsd* pool) {
+// tr: rows per staged tile (0: tile_rows(r); else a multiple of 16 below it)
+__device__ __forceinline__ Lay make_lay(int r, int tr, ldsd* pool) {
   Lay L;
   L.r = r;
   L.ld = lds_ld(r);
-  L.tr = tile_rows(r);
+  L.tr = tr ? tr : tile_rows(r);
   const int mat = r * L.ld;
   L.A = pool;
   L.B = L.A + mat;
@@ -233,10 +244,12 @@ enum { W_NONE = 0, W_M = 1, W_BT = 2 };
 
 // With rbf16 the product written to Outp (and kept for the Gram) is rounded to
 // BF16 precision (round to nearest even) before it is stored in TO.
+// gp: the Gram partials of a cooperative grid ([G][nb][256], null for one
+// workgroup).
 template <typename TO>
 __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restrict__ S, int64_t m,
                                             int wsel, TO* Outp, TO* Out2p, bool gram,
-                                            bool rbf16 = false) {
+                                            double* gp, bool rbf16 = false) {
   const int r = L.r, ld = L.ld, tr = L.tr;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -244,6 +257,9 @@ __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restri
   const int nk = (r + 3) >> 2;             // K steps of the product (<= 16)
   const int cap = tr * r;                  // elements of a full tile
   const int64_t ntile = (m + tr - 1) / tr;
+  // this workgroup's row tiles [t_lo, t_hi)
+  const int64_t nwg = gridDim.x, wg = blockIdx.x;
+  const int64_t t_lo = ntile * wg / nwg, t_hi = ntile * (wg + 1) / nwg;
   const bool apply = wsel != W_NONE;
   const int trans = wsel == W_BT;
   const ldsd* Wm = (wsel == W_BT) ? L.B : L.M;
@@ -295,13 +311,13 @@ __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restri
   };
 #pragma unroll
   for (int b = 0; b < PF; ++b)
-    if (b < ntile) load(buf[b], b);
+    if (t_lo + b < t_hi) load(buf[b], t_lo + b);
 
-  for (int64_t t0 = 0; t0 < ntile; t0 += PF) {
+  for (int64_t t0 = t_lo; t0 < t_hi; t0 += PF) {
 #pragma unroll
     for (int b = 0; b < PF; ++b) {
       const int64_t t = t0 + b;
-      if (t < ntile) {
+      if (t < t_hi) {
         const int64_t i0 = t * tr;
         const int rows = (int)((m - i0) < tr ? (m - i0) : tr);
         const int cnt = rows * r;
@@ -311,7 +327,7 @@ __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restri
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
           if (j * NT + tid < cap) Ti[off[j]] = buf[b][j];
-        if (t + PF < ntile) load(buf[b], t + PF);
+        if (t + PF < t_hi) load(buf[b], t + PF);
         __syncthreads();
         if (Out2p) {
 #pragma unroll
@@ -391,11 +407,25 @@ __device__ __forceinline__ void stream_pass(const Lay& L, const double* __restri
       for (int v = 0; v < 4; ++v) part[(ks * nb + blk) * 256 + (lk + 4 * v) * 16 + lr] = gacc[v];
     }
     __syncthreads();
+    if (gp) {
+      // this workgroup's partial to the buffer, then the grid's in order
+      for (int e = tid; e < nb * 256; e += NT) {
+        double sum = 0.0;
+        for (int q = 0; q < nsplit; ++q) sum += part[q * nb * 256 + e];
+        gp[wg * nb * 256 + e] = sum;
+      }
+      cooperative_groups::this_grid().sync();
+    }
     ldsd* G = L.A;
     for (int e = tid; e < nb * 256; e += NT) {
       const int bq = e >> 8, rc = e & 255, row = rc >> 4, col = rc & 15;
       double sum = 0.0;
-      for (int q = 0; q < nsplit; ++q) sum += part[(q * nb + bq) * 256 + rc];
+      if (gp) {
+#pragma unroll 8
+        for (int64_t q = 0; q < nwg; ++q) sum += gp[q * nb * 256 + e];
+      } else {
+        for (int q = 0; q < nsplit; ++q) sum += part[(q * nb + bq) * 256 + rc];
+      }
       int xa = 0, xb = 0;
       for (int p = 0, x = 0; x < nt; ++x)
         for (int y = x; y < nt; ++y, ++p)
@@ -414,7 +444,7 @@ template <typename TQ>
 __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
   __shared__ double pool[POOL];
   __shared__ double red[NW];
-  const Lay L = make_lay(a.r, (ldsd*)pool);
+  const Lay L = make_lay(a.r, a.tr, (ldsd*)pool);
   const int r = a.r, ld = L.ld, tid = threadIdx.x;
   const int64_t m = a.m;
   const int tpr = NT / r;
@@ -422,6 +452,8 @@ __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
   const double* src = a.Qin;    // PREP source unless SOLVE or QR runs
   bool have_gram = false;       // L.A holds the Gram of src
   const bool prep = (a.ops & STEP_PREP) != 0;
+  const bool lead = tid == 0 && blockIdx.x == 0;   // writes the scalar outputs
+  double* gp = gridDim.x > 1 ? a.gpart : nullptr;
 
   if (a.ops & STEP_SOLVE) {
     if (ri < r)
@@ -431,7 +463,7 @@ __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
       }
     __syncthreads();
     if (belim(L.A, L.B, r, ld)) {
-      if (tid == 0) *a.status = TK_ERR_RANK_DEFICIENT;
+      if (lead) *a.status = TK_ERR_RANK_DEFICIENT;
       return;
     }
     // tr(Gq^{-1} G_V) = ||Wq D||_F^2 with Wq = Cq^{-1} (Gq = Cq Cq^T) and
@@ -450,7 +482,7 @@ __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
     for (int o = 32; o >= 1; o >>= 1) e2 += __shfl_xor(e2, o);
     if ((tid & 63) == 0) red[tid >> 6] = e2;
     __syncthreads();
-    if (tid == 0) {
+    if (lead) {
       double e = 0.0;
       for (int w = 0; w < NW; ++w) e += red[w];
       a.res2[0] = a.rsum ? a.rsum[0] : ((a.norm2p ? a.norm2p[0] : a.norm2) - e);
@@ -459,57 +491,93 @@ __global__ __launch_bounds__(NT, 1) void k_mode_step(StepArgs a) {
     // L_{k+1} = L_acc G_V^{-1}, with the Gram of L_{k+1} for PREP
     bscale(L.A, L.B, r, ld);
     bwtw(L.B, r, ld, L.M);
-    stream_pass<double>(L, a.Lacc, m, W_M, a.Lnext, nullptr, prep);
+    stream_pass<double>(L, a.Lacc, m, W_M, a.Lnext, nullptr, prep, gp);
     have_gram = prep;
     src = a.Lnext;
   }
 
   if (a.ops & STEP_QR) {
     // CholeskyQR2: Q1 = L C1^{-T}, Q = Q1 C2^{-T}
-    stream_pass<double>(L, a.Qin, m, W_NONE, nullptr, nullptr, true);
+    stream_pass<double>(L, a.Qin, m, W_NONE, nullptr, nullptr, true, gp);
     if (belim(L.A, L.B, r, ld)) {
-      if (tid == 0) *a.status = TK_ERR_RANK_DEFICIENT;
+      if (lead) *a.status = TK_ERR_RANK_DEFICIENT;
       return;
     }
     bscale(L.A, L.B, r, ld);
-    stream_pass<double>(L, a.Qin, m, W_BT, a.Q1, nullptr, true);
+    stream_pass<double>(L, a.Qin, m, W_BT, a.Q1, nullptr, true, gp);
     if (belim(L.A, L.B, r, ld)) {
-      if (tid == 0) *a.status = TK_ERR_RANK_DEFICIENT;
+      if (lead) *a.status = TK_ERR_RANK_DEFICIENT;
       return;
     }
     bscale(L.A, L.B, r, ld);
-    stream_pass<double>(L, a.Q1, m, W_BT, a.Qout, nullptr, prep);
+    stream_pass<double>(L, a.Q1, m, W_BT, a.Qout, nullptr, prep, gp);
     have_gram = prep;
     src = a.Qout;
   }
 
   if (prep && src) {
     int* pst = (a.ops & STEP_PREP_SPECULATIVE) ? a.prep_status : a.status;
-    if (!have_gram) stream_pass<double>(L, src, m, W_NONE, nullptr, nullptr, true);
+    if (!have_gram) stream_pass<double>(L, src, m, W_NONE, nullptr, nullptr, true, gp);
     if (belim(L.A, L.B, r, ld)) {
-      if (tid == 0) *pst = TK_ERR_RANK_DEFICIENT;
+      if (lead) *pst = TK_ERR_RANK_DEFICIENT;
       return;
     }
     bscale(L.A, L.B, r, ld);
     bwtw(L.B, r, ld, L.M);
     // L~ = L (L^T L)^{-1} in TQ (BF16 precision with lq_bf16), with the Gram
     // of the quantised L~
-    stream_pass<TQ>(L, src, m, W_M, (TQ*)a.Lq, (TQ*)a.Lr, true, a.lq_bf16 != 0);
+    stream_pass<TQ>(L, src, m, W_M, (TQ*)a.Lq, (TQ*)a.Lr, true, gp, a.lq_bf16 != 0);
     if (belim(L.A, L.B, r, ld)) {
-      if (tid == 0) *pst = TK_ERR_RANK_DEFICIENT;
+      if (lead) *pst = TK_ERR_RANK_DEFICIENT;
       return;
     }
     bscale(L.A, L.B, r, ld);
-    if (ri < r)
+    if (ri < r && blockIdx.x == 0)
       for (int j = rc; j < r; j += tpr) a.Wq[ri * r + j] = L.B[ri * ld + j];
   }
 }
 
 }  // namespace
 
+constexpr int GRID_MAX = 32;      // workgroups of a cooperative mode step
+constexpr int GRID_ROWS = 64;     // rows per workgroup it aims at
+// A cooperative launch leaves about 11 us idle before and after the kernel on
+// this runtime (measured in kernel traces; plain launches follow each other
+// without a gap), so the grid is used only where the m x r passes take a few
+// hundred microseconds on one workgroup: m r^2 at least GRID_MIN_WORK (the
+// 1024 x 48 mode step passes take about 230 us there, 200 x 20 about 40 us).
+constexpr int64_t GRID_MIN_WORK = 1000000;
+
 void launch_mode_step(const StepArgs& a, int q_dtype, hipStream_t s) {
-  if (q_dtype == TK_F64) hipLaunchKernelGGL(k_mode_step<double>, dim3(1), dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL(k_mode_step<float>, dim3(1), dim3(NT), 0, s, a);
+  // with a partial buffer: one row tile of about GRID_ROWS rows per
+  // workgroup (at most GRID_MAX workgroups, partials within the buffer)
+  StepArgs arg = a;
+  arg.tr = 0;
+  int g = 1;
+  if (a.gpart && a.m > GRID_ROWS && a.m * a.r * a.r >= GRID_MIN_WORK) {
+    const int nt = (a.r + 15) / 16, nb = nt * (nt + 1) / 2;
+    const int trmax = tile_rows(a.r);
+    int64_t gm = ceil_div(a.m, GRID_ROWS);
+    if (gm > GRID_MAX) gm = GRID_MAX;
+    if (gm * nb * 256 > a.gpart_cap) gm = a.gpart_cap / (nb * 256);
+    if (gm > 1) {
+      int tr = (int)(ceil_div(ceil_div(a.m, gm), 16) * 16);
+      if (tr > trmax) tr = trmax;
+      const int64_t ntile = ceil_div(a.m, tr);
+      g = (int)(ntile < gm ? ntile : gm);
+      if (g > 1) arg.tr = tr;
+      else g = 1;
+    }
+  }
+  const void* fn = q_dtype == TK_F64 ? (const void*)k_mode_step<double>
+                                     : (const void*)k_mode_step<float>;
+  if (g == 1) {
+    void* args[] = {&arg};
+    (void)hipLaunchKernel(fn, dim3(1), dim3(NT), args, 0, s);
+  } else {
+    void* args[] = {&arg};
+    (void)hipLaunchCooperativeKernel(fn, dim3(g), dim3(NT), args, 0, s);
+  }
 }
 
 }  // namespace tk

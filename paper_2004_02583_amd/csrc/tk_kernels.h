@@ -151,6 +151,10 @@ struct StepArgs {
   void* Lq; void* Lr; double* Wq; int lq_bf16;
   int* status;        // failures of SOLVE / QR / non-speculative PREP
   int* prep_status;   // failures of a speculative PREP
+  // optional FP64 buffer of gpart_cap doubles for the Gram partials of a
+  // cooperative multi-workgroup launch (null: one workgroup)
+  double* gpart; int64_t gpart_cap;
+  int tr;             // rows per staged tile (set by launch_mode_step)
 };
 void launch_mode_step(const StepArgs& a, int q_dtype, hipStream_t s);
 

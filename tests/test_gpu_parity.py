@@ -114,7 +114,8 @@ def test_contract_allbut_parity(gpu_lib, dt):
 STEP_CASES = [((20, 30, 40), 0, 5), ((20, 30, 40), 1, 7), ((20, 30, 40), 2, 6),
               ((100, 9, 70), 0, 20), ((12, 11, 10, 9), 2, 4),
               ((30, 64, 50), 1, 18),      # second rank tile mostly padding, I = 64, tiles straddle p
-              ((40, 150, 30), 1, 19)]     # second rank tile mostly padding, ragged row tiles
+              ((40, 150, 30), 1, 19),     # second rank tile mostly padding, ragged row tiles
+              ((1024, 60), 0, 48)]        # m r^2 > 10^6: the mode step on a grid of workgroups
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
