@@ -9,9 +9,9 @@
 //           registers while the current one is worked on);
 //   Gram    G_V += V^T V from the finished V (FP32 per tile, FP64 across;
 //           wave w < NR (NR + 1) / 2 owns one 16 x 16 block pair);
-//   pass 2  L_acc[chunk rows] += X_c V  (L-update), the chunks read again:
-//           the second read of a tile is served by the caches (L2 / MALL),
-//           so HBM traffic stays one read per sweep.
+//   pass 2  L_acc[chunk rows] += X_c V  (L-update), the chunks read again,
+//           last-loaded first, partly from the caches (a tile's 256 KiB per
+//           workgroup overflows the XCD's L2).
 // L_acc stays in registers for the whole launch: wave w owns, in every chunk,
 // the output tiles (16 rows x 16 ranks) w, w + 8, ... of the 8 NR tiles of the
 // chunk.  The R-update splits each chunk's 128 rows in two 64-row halves so the
@@ -319,14 +319,19 @@ __global__ void __launch_bounds__(NT, 1) k_fused_big(FusedArgs a) {
         __builtin_amdgcn_sched_barrier(0);
       }
     };
-    load_chunk<T, LAYOUT>(X, v, j0, 0, lane, w, pf, pf_ok);
-    for (int c = 0; c < NCH; ++c) {
+    // (after pass 1 the chunks are read back last-loaded first: the freshest
+    // lines are the likeliest still in L2, where a repeat of pass 1's order
+    // would evict each chunk just before it is needed)
+    auto ord = [&](int k) __attribute__((always_inline)) { return MODE == 0 ? NCH - 1 - k : k; };
+    load_chunk<T, LAYOUT>(X, v, j0, ord(0), lane, w, pf, pf_ok);
+    for (int k = 0; k < NCH; ++k) {
+      const int c = ord(k);
       __syncthreads();
       if (MODE == 2 && want_norm)
         stash_chunk<T, LAYOUT, true>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
       else stash_chunk<T, LAYOUT, false>(v, j0, c, lane, w, pf, pf_ok, Xs, nsum);
       __syncthreads();
-      if (c + 1 < NCH) load_chunk<T, LAYOUT>(X, v, j0, c + 1, lane, w, pf, pf_ok);
+      if (k + 1 < NCH) load_chunk<T, LAYOUT>(X, v, j0, ord(k + 1), lane, w, pf, pf_ok);
       switch (c) {
         case 0: lupd(lacc[0]); break;
         case 1: lupd(lacc[1]); break;
