@@ -363,6 +363,38 @@ def test_rank_deficient_status(gpu_lib):
     assert e.value.code == -4
 
 
+def test_rank_deficient_status_grid_mode_step(gpu_lib):
+    """Remark 3's rank test inside the mode step that runs on a grid of
+    workgroups (m R^2 >= 10^6): a mode of exact rank 3 asked for R = 48 fails
+    its initial QR on every workgroup alike, and the call reports it for that
+    mode (the modes after it are skipped)."""
+    import ctypes
+    from paper_2004_02583_amd import _lib as L
+    tk = gpu_lib
+    flush("rank deficient, grid mode step")
+    rng = np.random.default_rng(31)
+    A = to_gpu(synth.tucker_lowrank(rng, (1024, 8, 8), (3, 3, 3), 0.0)[0], "f64")
+    ranks = (48, 8, 8)
+    lib = L.lib()
+    dims = L.i64arr(A.shape)
+    rk = L.i32arr(ranks)
+    need = lib.als_workspace_bytes(1, L.TK_F64, 3, dims, rk)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    Us = [torch.empty((A.shape[n], ranks[n]), dtype=torch.float64, device="cuda") for n in range(3)]
+    G = torch.empty(ranks, dtype=torch.float64, device="cuda")
+    info = L.tk_als_info()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = lib.als_sthosvd(ctypes.c_void_p(A.data_ptr()), L.TK_F64, 3, dims, rk, None,
+                         L.ptrarr([u.data_ptr() for u in Us]), ctypes.c_void_p(G.data_ptr()),
+                         ctypes.c_void_p(ws.data_ptr()), need, ctypes.byref(info), stream)
+    torch.cuda.synchronize()
+    assert rc == -4 and info.status == -4
+    assert list(info.mode_status)[:3] == [-4, 2, 2]
+    with pytest.raises(tk.TuckerALSError) as e:
+        tk.als_thosvd(A, ranks, tol=1e-6)
+    assert e.value.code == -4
+
+
 @pytest.mark.parametrize("dt", ["f64"])
 def test_mode_status_report(gpu_lib, dt):
     """Per-mode status through the C ABI: the failing mode carries the error (Remark 3),
