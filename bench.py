@@ -21,6 +21,9 @@ Beside the headline line, the same JSON carries BF16 storage on the same
 workload (time to tolerance against plain FP32), the 512-tensor batched
 workload, and the 1024^3 t-HOSVD-ALS workload in FP32 and BF16 storage
 (`large_*` keys; `--no-large` skips it, `--only-large` runs it alone).
+`--paper-tucker` times, alone, the paper's largest 4-way Tucker test case
+(Section 6.1.2: 5000 x 100^3 FP32, 20 GB), whose first mode (I = 5000,
+R = 50) is beyond the fused kernels and runs on the generic two-pass path.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -227,6 +230,36 @@ def cpu_baseline(A, ncols=8_000_000, sweeps=3):
                        f"{dt:.1f} s; bytes counted as FP32 (4 B/element) per sweep")
 
 
+def bench_paper_tucker(tk, steps, I=5000, eta=1e-4):
+    """Section 6.1.2's largest case: I x 100^3 FP32, core (I/100, 10, 10, 10) with
+    entries U[5, 10] times orthonormal factors plus 1e-4 absolute Gaussian noise
+    (seeded, generated on the GPU); t- and st-HOSVD-ALS to the core dims."""
+    import torch
+    from workloads import synth
+    log(f"generating the {I} x 100^3 Tucker test case on the GPU")
+    Ah, A, _, _ = synth.tucker_paper_torch(6, I, out_dtype=torch.float32)
+    del A
+    torch.cuda.empty_cache()
+    ranks = (max(1, round(0.01 * I)), 10, 10, 10)
+    out = {"paper_tucker_workload": f"{I} x 100^3 FP32 ({Ah.numel() * 4 / 1e9:.1f} GB), core "
+                                    f"{ranks} U[5,10] x orthonormal factors + 1e-4 absolute "
+                                    f"noise, eta {eta}"}
+    for which, run in (("st", tk.als_sthosvd), ("t", tk.als_thosvd)):
+        G, Us, info = run(Ah, ranks, tol=eta)          # warm-up
+        del G, Us
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            G, Us, info = run(Ah, ranks, tol=eta)
+            del G, Us
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        log(f"{I} x 100^3 {which}-HOSVD-ALS: {dt * 1e3:.1f} ms, iters {info['iters']}")
+        out[f"paper_tucker_{which}_ms"] = round(dt * 1e3, 2)
+        out[f"paper_tucker_{which}_iters"] = info["iters"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +271,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 t-HOSVD leg")
     ap.add_argument("--only-large", action="store_true",
                     help="run the 1024^3 t-HOSVD leg alone (for profiling its kernels)")
+    ap.add_argument("--paper-tucker", action="store_true",
+                    help="time the paper's largest Tucker test case (5000 x 100^3) alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
@@ -256,6 +291,9 @@ def main():
         copy_calibration()
     if args.only_large:
         print(json.dumps(bench_large(tk, max(1, min(args.steps, 3)))), flush=True)
+        return
+    if args.paper_tucker:
+        print(json.dumps(bench_paper_tucker(tk, max(1, min(args.steps, 3)))), flush=True)
         return
     log("generating 200^4 FP32 workload on the GPU")
     w = synth.workload_4way_torch(DIMS, RANK, 1e-4, device=dev)

@@ -58,9 +58,82 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ X, const View& v
   }
 }
 
+// The X and W elements of one row step (rows i0 .. i0 + TI - 1) that thread
+// tid stages, loaded into registers (zero outside), and their LDS stores:
+// while a step is computed from LDS the next step's loads are in flight.
+template <typename T, typename C, int OM>
+struct StepRegs {
+  static constexpr int NX = TI * TJ / 256, NW = TI * OM / 256;
+  C x[NX], w[NW];
+};
+
+// Element k of thread tid: X row i0 + tid / TJ + 4k of fibre j0 + tid % TJ
+// (Q > 1), or row i0 + tid % TI of fibre j0 + tid / TI + 4k (Q == 1); W row
+// i0 + tid / OM + (256 / OM) k, output o0 + tid % OM.  The per-thread bases
+// pass through empty asm statements, so that each step forms its addresses
+// from them plus wave-uniform offsets instead of keeping per-element
+// addresses hoisted out of the row loop (they would take the registers).
+template <typename T, typename C, int OM>
+__device__ __forceinline__ void step_load(const T* __restrict__ X, const C* __restrict__ W,
+                                          const VpassArgs& a, const View& v, int64_t i0,
+                                          int64_t j0, int64_t o0,
+                                          const int64_t* __restrict__ fb,
+                                          StepRegs<T, C, OM>& sr) {
+  const int64_t J = v.J();
+  const int tid = (int)threadIdx.x;
+  if (v.Q == 1) {
+    const int ii = tid % TI;
+    const int64_t i = i0 + ii;
+#pragma unroll
+    for (int k = 0; k < StepRegs<T, C, OM>::NX; ++k) {
+      const int jj = tid / TI + 4 * k;
+      C val = 0;
+      if (i < v.I && j0 + jj < J) val = (C)Elem<T>::load(X + fb[jj] + i);
+      sr.x[k] = val;
+    }
+  } else {
+    const int jj = tid % TJ;
+    const bool jok = j0 + jj < J;
+    const int64_t ib = i0 + tid / TJ;
+    const T* xb = X + fb[jj] + ib * v.Q;
+    asm volatile("" : "+v"(xb));
+#pragma unroll
+    for (int k = 0; k < StepRegs<T, C, OM>::NX; ++k) {
+      C val = 0;
+      if (jok && ib + 4 * k < v.I) val = (C)Elem<T>::load(xb + (int64_t)(4 * k) * v.Q);
+      sr.x[k] = val;
+    }
+  }
+  const int64_t iw = i0 + tid / OM, o = o0 + tid % OM;
+  const bool ook = o < a.O;
+  const C* wb = W + iw * a.w_ldi + o * a.w_ldo;
+  asm volatile("" : "+v"(wb));
+#pragma unroll
+  for (int k = 0; k < StepRegs<T, C, OM>::NW; ++k) {
+    constexpr int DI = 256 / OM;
+    sr.w[k] = (ook && iw + DI * k < v.I) ? wb[(int64_t)(DI * k) * a.w_ldi] : (C)0;
+  }
+}
+
+template <typename T, typename C, int OM>
+__device__ __forceinline__ void step_store(const View& v, const StepRegs<T, C, OM>& sr, C* xt,
+                                           C* wt) {
+#pragma unroll
+  for (int k = 0; k < StepRegs<T, C, OM>::NX; ++k) {
+    const int e = (int)threadIdx.x + 256 * k;
+    int ii, jj;
+    if (v.Q == 1) { ii = e % TI; jj = e / TI; }
+    else { jj = e % TJ; ii = e / TJ; }
+    xt[ii * LDX + jj] = sr.x[k];
+  }
+#pragma unroll
+  for (int k = 0; k < StepRegs<T, C, OM>::NW; ++k) wt[(int)threadIdx.x + 256 * k] = sr.w[k];
+}
+
 // ---------------------------------------------------------------------------
 // out(j, o) = sum_i W(i, o) X[j-th fibre][i]; thread (jj, oq) owns outputs
-// o = o0 + oq + 4k of fibre j0 + jj.
+// o = o0 + oq + 4k of fibre j0 + jj.  Row steps of TI rows; the next step's
+// X and W elements are loaded into registers while a step is computed.
 template <typename T, typename C, int OM>
 __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
   __shared__ C xt[TI * LDX];
@@ -86,16 +159,16 @@ __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
       C acc[OM / 4];
 #pragma unroll
       for (int k = 0; k < OM / 4; ++k) acc[k] = 0;
+      StepRegs<T, C, OM> sr;
+      step_load<T, C, OM>(X, W, a, v, 0, j0, o0, fb, sr);
       for (int64_t i0 = 0; i0 < v.I; i0 += TI) {
         __syncthreads();
-        load_tile<T, C>(X, v, i0, j0, fb, xt);
-        for (int e = threadIdx.x; e < TI * OM; e += blockDim.x) {
-          int ii = e / OM, oo = e % OM;
-          int64_t i = i0 + ii, o = o0 + oo;
-          wt[e] = (i < v.I && o < a.O) ? W[i * a.w_ldi + o * a.w_ldo] : (C)0;
-        }
+        step_store<T, C, OM>(v, sr, xt, wt);
         __syncthreads();
+        if (i0 + TI < v.I) step_load<T, C, OM>(X, W, a, v, i0 + TI, j0, o0, fb, sr);
         const int rows = (int)((v.I - i0) < TI ? (v.I - i0) : TI);
+        // (a modest unroll: the registers go to the loads in flight)
+#pragma unroll 4
         for (int ii = 0; ii < rows; ++ii) {
           C x = xt[ii * LDX + jj];
 #pragma unroll
@@ -114,29 +187,38 @@ __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
       }
     }
     if (a.Lr) {
-      // explicit residual of this tile: sum_j ||x_j - Lr v_j||^2 (O <= OM)
-      const C* Lr = (const C*)a.Lr;
+      // explicit residual of this tile: sum_j ||x_j - Lr v_j||^2 (O <= OM).
+      // v_j comes back from the output into LDS with an odd row stride (a
+      // stride of OM would put every lane of a read on one bank) and then
+      // into this thread's registers; Lr and X stream by row steps as above.
       const C* V = (const C*)a.out;
-      __shared__ C vt[TJ * OM];
+      __shared__ C vt[TJ * (OM + 1)];
       __syncthreads();
       for (int e = threadIdx.x; e < TJ * OM; e += blockDim.x) {
         int jl = e / OM, o = e % OM;
-        vt[e] = (j0 + jl < J && o < a.O) ? V[(j0 + jl) * a.O + o] : (C)0;
+        vt[jl * (OM + 1) + o] = (j0 + jl < J && o < a.O) ? V[(j0 + jl) * a.O + o] : (C)0;
       }
+      __syncthreads();
+      C vr[OM];
+#pragma unroll
+      for (int o = 0; o < OM; ++o) vr[o] = vt[jj * (OM + 1) + o];
+      VpassArgs ar = a;
+      ar.W = a.Lr;
+      ar.w_ldi = a.O;
+      ar.w_ldo = 1;
+      StepRegs<T, C, OM> sr;
+      step_load<T, C, OM>(X, (const C*)a.Lr, ar, v, 0, j0, 0, fb, sr);
       for (int64_t i0 = 0; i0 < v.I; i0 += TI) {
         __syncthreads();
-        load_tile<T, C>(X, v, i0, j0, fb, xt);
-        for (int e = threadIdx.x; e < TI * OM; e += blockDim.x) {
-          int ii = e / OM, o = e % OM;
-          int64_t i = i0 + ii;
-          wt[e] = (i < v.I && o < a.O) ? Lr[i * a.O + o] : (C)0;
-        }
+        step_store<T, C, OM>(v, sr, xt, wt);
         __syncthreads();
+        if (i0 + TI < v.I) step_load<T, C, OM>(X, (const C*)a.Lr, ar, v, i0 + TI, j0, 0, fb, sr);
         const int rows = (int)((v.I - i0) < TI ? (v.I - i0) : TI);
         if (j < J) {
           for (int ii = oq; ii < rows; ii += 4) {
             C d = xt[ii * LDX + jj];
-            for (int o = 0; o < OM; ++o) d -= wt[ii * OM + o] * vt[jj * OM + o];
+#pragma unroll
+            for (int o = 0; o < OM; ++o) d -= wt[ii * OM + o] * vr[o];
             rsum += (double)d * (double)d;
           }
         }
