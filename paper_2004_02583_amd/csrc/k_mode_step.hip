@@ -571,13 +571,14 @@ void launch_mode_step(const StepArgs& a, int q_dtype, hipStream_t s) {
   }
   const void* fn = q_dtype == TK_F64 ? (const void*)k_mode_step<double>
                                      : (const void*)k_mode_step<float>;
-  if (g == 1) {
-    void* args[] = {&arg};
-    (void)hipLaunchKernel(fn, dim3(1), dim3(NT), args, 0, s);
-  } else {
-    void* args[] = {&arg};
-    (void)hipLaunchCooperativeKernel(fn, dim3(g), dim3(NT), args, 0, s);
+  void* args[] = {&arg};
+  if (g > 1) {
+    if (hipLaunchCooperativeKernel(fn, dim3(g), dim3(NT), args, 0, s) == hipSuccess) return;
+    // no cooperative launch: the one-workgroup form computes the same step
+    (void)hipGetLastError();
+    arg.tr = 0;
   }
+  (void)hipLaunchKernel(fn, dim3(1), dim3(NT), args, 0, s);
 }
 
 }  // namespace tk

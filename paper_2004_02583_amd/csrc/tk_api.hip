@@ -285,6 +285,16 @@ void init_enqueue(const void* X, int xdt, const View& v, int R, uint64_t seed, i
   }
 }
 
+// The mode step may run on a cooperative grid with its Gram partials in the
+// sweep's G_V partial buffer (free while it runs: G_V is reduced before, and
+// the next fused pass writes it after).  Not in the allocation-free entry
+// point, whose callers may capture the stream into a graph.
+void mode_step_grid(StepArgs& a, ModeWs& w, int R) {
+  if (t_no_alloc) return;
+  a.gpart = w.gparts;
+  a.gpart_cap = (int64_t)NWG_MAX * R * R;
+}
+
 // The step that follows the initial pass: L = Q of the reduced QR of Lacc,
 // then L~, its quantised Gram factor (and L for the explicit residual) for
 // the first sweep.
@@ -293,7 +303,7 @@ void init_finish_enqueue(const View& v, int R, int xdt, int resid_mode, ModeWs& 
   StepArgs a{};
   a.m = v.I; a.r = R; a.ops = STEP_QR | STEP_PREP;
   a.Qin = w.Lacc; a.Q1 = w.Q1; a.Qout = w.L;
-  a.gpart = w.gparts; a.gpart_cap = (int64_t)NWG_MAX * R * R;   // free between passes
+  mode_step_grid(a, w, R);
   a.Lq = w.Lq; a.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; a.Wq = w.Wq;
   a.lq_bf16 = lq_rounded(xdt, resid_mode);
   a.status = &w.st->status; a.prep_status = &w.st->prep_status[0];
@@ -351,7 +361,7 @@ void sweep_enqueue(const void* X, int xdt, const View& v, int R, double norm2,
   StepArgs a{};
   a.m = v.I; a.r = R; a.ops = STEP_SOLVE | STEP_PREP | STEP_PREP_SPECULATIVE;
   a.Lacc = w.Lacc; a.GV = w.GV; a.Lnext = w.Lnext; a.norm2 = norm2; a.norm2p = norm2p;
-  a.gpart = w.gparts; a.gpart_cap = (int64_t)NWG_MAX * R * R;   // G_V is reduced by now
+  mode_step_grid(a, w, R);
   if (expl) {
     launch_reduce_parts<double>(w.sparts, nres, 1, 1, &w.st->rsum, w.rtmp, s);
     a.rsum = &w.st->rsum;
@@ -1183,7 +1193,7 @@ int als_sweep_step(const void* A, int32_t a_dtype, int32_t N, const int64_t* dim
     StepArgs p{};
     p.m = v.I; p.r = R; p.ops = STEP_PREP;
     p.Qin = w.L;
-    p.gpart = w.gparts; p.gpart_cap = (int64_t)NWG_MAX * R * R;
+    mode_step_grid(p, w, R);
     p.Lq = w.Lq; p.Lr = resid_mode == TK_RESID_EXPLICIT ? w.Lr : nullptr; p.Wq = w.Wq;
     p.lq_bf16 = lq_rounded(a_dtype, resid_mode);
     p.status = &w.st->status; p.prep_status = &w.st->prep_status[0];
