@@ -131,9 +131,11 @@ __device__ __forceinline__ void step_store(const View& v, const StepRegs<T, C, O
 }
 
 // ---------------------------------------------------------------------------
-// out(j, o) = sum_i W(i, o) X[j-th fibre][i]; thread (jj, oq) owns outputs
-// o = o0 + oq + 4k of fibre j0 + jj.  Row steps of TI rows; the next step's
-// X and W elements are loaded into registers while a step is computed.
+// out(j, o) = sum_i W(i, o) X[j-th fibre][i]; thread (jh, oh) owns outputs
+// o = o0 + oh + 8k of fibres j0 + jh and j0 + jh + 32 (two fibres per
+// thread: each W value read from LDS serves two products).  Row steps of TI
+// rows; the next step's X and W elements are loaded into registers while a
+// step is computed.
 template <typename T, typename C, int OM>
 __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
   __shared__ C xt[TI * LDX];
@@ -144,7 +146,9 @@ __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
   const C* W = (const C*)a.W;
   const View v = a.v;
   const int64_t J = v.J();
-  const int jj = threadIdx.x % TJ, oq = threadIdx.x / TJ;
+  const int jj = threadIdx.x % TJ, oq = threadIdx.x / TJ;    // residual
+  constexpr int HJ = TJ / 2;
+  const int jh = threadIdx.x % HJ, oh = threadIdx.x / HJ;    // products
   const int64_t ntiles = ceil_div(J, TJ);
   double rsum = 0.0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -153,12 +157,10 @@ __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
     tile_bases(v, j0, fb);
     __syncthreads();
     const int64_t j = j0 + jj;
-    int64_t p = 0, q = 0;
-    if (j < J) { p = j / v.Q; q = j - p * v.Q; }
     for (int64_t o0 = 0; o0 < a.O; o0 += OM) {
-      C acc[OM / 4];
+      C acc0[OM / 8], acc1[OM / 8];
 #pragma unroll
-      for (int k = 0; k < OM / 4; ++k) acc[k] = 0;
+      for (int k = 0; k < OM / 8; ++k) acc0[k] = acc1[k] = 0;
       StepRegs<T, C, OM> sr;
       step_load<T, C, OM>(X, W, a, v, 0, j0, o0, fb, sr);
       for (int64_t i0 = 0; i0 < v.I; i0 += TI) {
@@ -170,18 +172,28 @@ __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
         // (a modest unroll: the registers go to the loads in flight)
 #pragma unroll 4
         for (int ii = 0; ii < rows; ++ii) {
-          C x = xt[ii * LDX + jj];
+          const C x0 = xt[ii * LDX + jh], x1 = xt[ii * LDX + jh + HJ];
 #pragma unroll
-          for (int k = 0; k < OM / 4; ++k) acc[k] += wt[ii * OM + oq + 4 * k] * x;
+          for (int k = 0; k < OM / 8; ++k) {
+            const C ww = wt[ii * OM + oh + 8 * k];
+            acc0[k] += ww * x0;
+            acc1[k] += ww * x1;
+          }
         }
       }
-      if (j < J) {
 #pragma unroll
-        for (int k = 0; k < OM / 4; ++k) {
-          int64_t o = o0 + oq + 4 * k;
-          if (o < a.O) {
-            if (a.out_kind == 0) ((C*)a.out)[j * a.O + o] = acc[k];
-            else ((C*)a.out)[(p * a.O + o) * v.Q + q] = acc[k];
+      for (int h = 0; h < 2; ++h) {
+        const int64_t jo = j0 + jh + HJ * h;
+        if (jo < J) {
+          const int64_t p = jo / v.Q, q = jo - (jo / v.Q) * v.Q;
+#pragma unroll
+          for (int k = 0; k < OM / 8; ++k) {
+            const int64_t o = o0 + oh + 8 * k;
+            const C val = h ? acc1[k] : acc0[k];
+            if (o < a.O) {
+              if (a.out_kind == 0) ((C*)a.out)[jo * a.O + o] = val;
+              else ((C*)a.out)[(p * a.O + o) * v.Q + q] = val;
+            }
           }
         }
       }
@@ -233,7 +245,9 @@ __global__ void __launch_bounds__(256) k_vpass(VpassArgs a) {
 
 // ---------------------------------------------------------------------------
 // Partial L(i, r) = sum_{j in chunk} X[j-th fibre][i] V(j, r); grid =
-// (i-blocks, fibre chunks); thread (ii, rq) owns r = rq + 4k of row i0+ii.
+// (i-blocks, fibre chunks); thread (ii, rq) owns r = rq + 8k of rows i0 + ii
+// and i0 + ii + 32 (two rows per thread: each V value read from LDS serves
+// two products).
 template <typename T, typename C, int RM, int VK>
 __global__ void __launch_bounds__(256) k_lpass(LpassArgs a, int64_t tiles_per_chunk) {
   __shared__ C xt[TI * LDX];
@@ -244,15 +258,16 @@ __global__ void __launch_bounds__(256) k_lpass(LpassArgs a, int64_t tiles_per_ch
   const T* X = (const T*)a.X;
   const View v = a.v;
   const int64_t J = v.J(), R = a.R;
-  const int ii = threadIdx.x % TI, rq = threadIdx.x / TI;
+  constexpr int HR = TI / 2;                 // second row of a thread
+  const int ii = threadIdx.x % HR, rq = threadIdx.x / HR;
   const int64_t i0 = (int64_t)blockIdx.x * TI;
   const int64_t c = blockIdx.y;
   const int64_t ntiles = ceil_div(J, TJ);
   const int64_t t_beg = c * tiles_per_chunk;
   const int64_t t_end = (t_beg + tiles_per_chunk < ntiles) ? t_beg + tiles_per_chunk : ntiles;
-  C acc[RM / 4];
+  C acc0[RM / 8], acc1[RM / 8];
 #pragma unroll
-  for (int k = 0; k < RM / 4; ++k) acc[k] = 0;
+  for (int k = 0; k < RM / 8; ++k) acc0[k] = acc1[k] = 0;
   double nsum = 0.0;
   for (int64_t tile = t_beg; tile < t_end; ++tile) {
     const int64_t j0 = tile * TJ;
@@ -286,17 +301,22 @@ __global__ void __launch_bounds__(256) k_lpass(LpassArgs a, int64_t tiles_per_ch
       }
     }
     for (int jl = 0; jl < TJ; ++jl) {
-      C x = xt[ii * LDX + jl];
+      const C x0 = xt[ii * LDX + jl], x1 = xt[(ii + HR) * LDX + jl];
 #pragma unroll
-      for (int k = 0; k < RM / 4; ++k) acc[k] += x * vt[jl * RM + rq + 4 * k];
+      for (int k = 0; k < RM / 8; ++k) {
+        const C vv = vt[jl * RM + rq + 8 * k];
+        acc0[k] += x0 * vv;
+        acc1[k] += x1 * vv;
+      }
     }
   }
-  if (i0 + ii < v.I) {
-    C* out = (C*)a.parts + c * v.I * R;
+  C* out = (C*)a.parts + c * v.I * R;
 #pragma unroll
-    for (int k = 0; k < RM / 4; ++k) {
-      int64_t r = rq + 4 * k;
-      if (r < R) out[(i0 + ii) * R + r] = acc[k];
+  for (int k = 0; k < RM / 8; ++k) {
+    const int64_t r = rq + 8 * k;
+    if (r < R) {
+      if (i0 + ii < v.I) out[(i0 + ii) * R + r] = acc0[k];
+      if (i0 + ii + HR < v.I) out[(i0 + ii + HR) * R + r] = acc1[k];
     }
   }
   if (a.norm2_parts) {
