@@ -277,8 +277,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not "
-              "part of it (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py: runs on exactly one GPU; runs on more than one GPU are not "
+              "supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
