@@ -294,8 +294,12 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
     if (MODE == 2 && want_norm) stash<T, LAYOUT, IC, true>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
     else stash<T, LAYOUT, IC, false>(v, j0, lane, w, pf, pf_ok, xrows, Xs, rsum);
     __syncthreads();
-    // this buffer now fetches the tile after the one the other buffer holds
-    prefetch<T, LAYOUT, IC>(X, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
+    // This buffer now fetches the tile after the one the other buffer holds.
+    // The older half of the waves issues its loads here; the younger half,
+    // whose issue would queue behind theirs, issues after its part of the
+    // R-update (the lighter one: with RM they take the four-rank remainder).
+    const bool early = w < NW / 2;
+    if (early) prefetch<T, LAYOUT, IC>(X, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
 
     if (MODE != 2) {
       // R-update: tile (fibre block f, rank tile n): A = X^T (16 fibres x
@@ -406,6 +410,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused(FusedArgs a) {
         Vf[jl * RS + r] = s;
       }
     }
+    if (!early) prefetch<T, LAYOUT, IC>(X, v, (tile + 2 * nwg) * TJ, lane, w, pf, pf_ok);
     __syncthreads();
 
     if (MODE == 3) {
