@@ -36,6 +36,8 @@ namespace tk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s4 lds_s4;
 
 namespace {
 
@@ -68,6 +70,22 @@ __host__ __device__ constexpr int rank_stride(int RP) { return (RP % 32 == 0) ? 
 // row is stored at chunk (f / 8) ^ (2 ((row / 8) & 3)).
 __device__ __forceinline__ int xidx(int row, int f) {
   return row * XS + ((((f >> 3) ^ (((row >> 3) & 3) << 1))) << 3) + (f & 7);
+}
+
+// The R-update's A operand: rows row0 .. row0 + 7 (row0 a multiple of 8) of
+// fibre f0 + j (j = lane % 16) of a tile, from two transposing LDS reads
+// (ds_read_b64_tr_b16): lane j of each 16-lane group points at the four
+// fibres f0 + 4 (j % 4) .. + 3 of row r0 + j / 4 and receives fibre f0 + j of
+// rows r0 .. r0 + 3.  The swizzle moves whole 8-fibre chunks and is the same
+// for the eight rows, so the four fibres stay contiguous and the second
+// read is four rows on.
+__device__ __forceinline__ bf8 rows8(const __bf16* x, int row0, int f0, int j) {
+  const __bf16* p0 = x + xidx(row0 + (j >> 2), f0 + 4 * (j & 3));
+  const s4 u0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(p0));
+  const s4 u1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(p0 + 4 * XS));
+  // (one whole-vector shuffle: element-wise inserts of these values are not
+  // reliably compiled)
+  return __builtin_bit_cast(bf8, __builtin_shufflevector(u0, u1, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
 struct LdsB {
@@ -206,16 +224,12 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16(FusedArgs a) {
       // R-update: fibre block w, all rank tiles; A = the eight rows
       // 32 st + 8 lk + e of fibre 16 w + lr (one swizzled column), B = the
       // three Lq^T splits of rank 16 n + lr over the same rows.
-      const int f = 16 * w + lr;
       f4 vacc[NR];
 #pragma unroll
       for (int n = 0; n < NR; ++n) vacc[n] = f4{0, 0, 0, 0};
       for (int st = 0; st < ST; ++st) {
         const int row0 = 32 * st + 8 * lk;
-        const __bf16* xc = Xs + xidx(row0, f);   // same swizzle for rows row0..row0+7
-        bf8 av;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
+        const bf8 av = rows8(Xs, row0, 16 * w, lr);
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
 #pragma unroll
@@ -518,11 +532,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
         const int row0 = 32 * st + 8 * lk;
 #pragma unroll
         for (int b = 0; b < NR; ++b) {
-          const int f = 16 * (w / NR + (NW / NR) * b) + lr;
-          const __bf16* xc = Xc + xidx(row0, f);
-          bf8 av;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) av[e] = xc[e * XS];
+          const bf8 av = rows8(Xc, row0, 16 * (w / NR + (NW / NR) * b), lr);
 #pragma unroll
           for (int s3 = 0; s3 < NS; ++s3) vacc[b] = mfma_bf16(av, bq[st][s3], vacc[b]);
         }
