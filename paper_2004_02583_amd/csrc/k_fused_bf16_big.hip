@@ -49,6 +49,8 @@ namespace tk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s4 lds_s4;
 
 namespace {
 
@@ -181,26 +183,36 @@ __device__ __forceinline__ void stash_chunk(const View& v, int64_t j0, int c, in
   }
 }
 
-// A operand of the R-update: rows row0..row0+7 of fibre f.
-template <int LAYOUT>
-__device__ __forceinline__ bf8 rupd_a(const __bf16* Xb, int row0, int f) {
-  if (LAYOUT == 1) return *(const bf8*)(Xb + cidx<1>(row0, f));
-  const __bf16* p = Xb + cidx<0>(row0, f);   // same swizzle for the eight rows
-  bf8 a;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) a[e] = p[e * RS0];
-  return a;
+// Eight BF16 values across the stored order, from two transposing LDS reads
+// (ds_read_b64_tr_b16).  The 16 lanes of a group cover four consecutive
+// lines of the buffer (rows in LAYOUT 0, fibres in LAYOUT 1) by 16 elements
+// along them: lane j points at elements 4 (j % 4) .. + 3 of line j / 4, and
+// receives element j of the four lines.  The second read is four lines on.
+// The chunk swizzle moves whole 8-element runs and is the same for eight
+// lines that start at a multiple of 8, so each lane's four elements are
+// contiguous.
+__device__ __forceinline__ bf8 tr8(const __bf16* p, int step) {
+  const s4 u0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(p));
+  const s4 u1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(p + step));
+  // (one whole-vector shuffle: element-wise inserts of these values are not
+  // reliably compiled)
+  return __builtin_bit_cast(bf8, __builtin_shufflevector(u0, u1, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
-// A operand of the L-update: fibres f0..f0+7 of row `row`.
+// A operand of the R-update: rows row0..row0+7 (row0 a multiple of 8) of
+// fibre f0 + j, j = lane % 16.
 template <int LAYOUT>
-__device__ __forceinline__ bf8 lupd_a(const __bf16* Xb, int row, int f0) {
-  if (LAYOUT == 0) return *(const bf8*)(Xb + cidx<0>(row, f0));
-  const __bf16* p = Xb + cidx<1>(row, f0);   // same swizzle for the eight fibres
-  bf8 a;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) a[e] = p[e * RS1];
-  return a;
+__device__ __forceinline__ bf8 rupd_a(const __bf16* Xb, int row0, int f0, int j) {
+  if (LAYOUT == 1) return *(const bf8*)(Xb + cidx<1>(row0, f0 + j));
+  return tr8(Xb + cidx<0>(row0 + (j >> 2), f0 + 4 * (j & 3)), 4 * RS0);
+}
+
+// A operand of the L-update: fibres f0..f0+7 (f0 a multiple of 8) of row
+// r0 + j, j = lane % 16.
+template <int LAYOUT>
+__device__ __forceinline__ bf8 lupd_a(const __bf16* Xb, int r0, int j, int f0) {
+  if (LAYOUT == 0) return *(const bf8*)(Xb + cidx<0>(r0 + j, f0));
+  return tr8(Xb + cidx<1>(r0 + 4 * (j & 3), f0 + (j >> 2)), 4 * RS1);
 }
 
 template <int NR, int LAYOUT, int NWK, int MODE>
@@ -326,11 +338,11 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
       // operands of the next 32-row block are read while this one's products
       // run)
       static_assert(NWK % 4 == 0, "a wave's R-update tiles share one fibre block");
-      const int fbw = 16 * (w & 3) + lr;
+      const int fb0 = 16 * (w & 3);
       bf8 av[2], bv[2][NU];
       auto rread = [&](int kb, int sl) __attribute__((always_inline)) {
         const int row0 = 32 * kb + 8 * lk;
-        av[sl] = rupd_a<LAYOUT>(Xb, row0, fbw);
+        av[sl] = rupd_a<LAYOUT>(Xb, row0, fb0, lr);
 #pragma unroll
         for (int u = 0; u < NU; ++u)
           if (u < nu)
@@ -410,7 +422,7 @@ __global__ void __launch_bounds__(64 * NWK, 1) k_fused_bf16_big(FusedArgs a) {
           bf8 av[RTW];
 #pragma unroll
           for (int i = 0; i < RTW; ++i)
-            av[i] = lupd_a<LAYOUT>(Xb, 16 * (w + NWK * i) + lr, 32 * ks + 8 * lk);
+            av[i] = lupd_a<LAYOUT>(Xb, 16 * (w + NWK * i), lr, 32 * ks + 8 * lk);
 #pragma unroll
           for (int n = 0; n < NR; ++n) {
 #pragma unroll
