@@ -147,6 +147,59 @@ __device__ __forceinline__ void stash(const View& v, int lane, int w, const uint
   if (NORM) nsum += (ns[0] + ns[1]) + (ns[2] + ns[3]);
 }
 
+// 16-byte form of the prefetch (Q a multiple of 8, 16-byte aligned tensor):
+// slot k is row 32k + 4w + lane / 16 (clamped) of the eight fibres
+// j0 + 8 (lane % 16) .. + 7, in pf[4k .. 4k + 3] (the same registers as the
+// dword form's 4 NSL slots, with a quarter of its load instructions).  The
+// eight never cross a row of the view, and a tile past the end is fetched in
+// bounds and staged as zeros.
+template <int NSL>
+__device__ __forceinline__ void prefetch16(const uint4* __restrict__ X16, const View& v,
+                                           int64_t j0, int lane, int w, uint32_t* pf, bool& ok) {
+  const int64_t J = v.J();
+  const int I = (int)v.I;
+  const int64_t j = j0 + 8 * (lane & 15);
+  ok = j < J;
+  const uint4* b = X16 + (v.fibre_base(ok ? j : J - 8) >> 3);
+  const int64_t q8 = v.Q >> 3;
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int ii = min(32 * k + 4 * w + (lane >> 4), I - 1);
+    const uint4 x = b[(int64_t)ii * q8];
+    pf[4 * k + 0] = x.x;
+    pf[4 * k + 1] = x.y;
+    pf[4 * k + 2] = x.z;
+    pf[4 * k + 3] = x.w;
+  }
+}
+
+// Stage the 16-byte slots: one 16-byte LDS store per slot (the swizzle moves
+// whole 8-fibre chunks); rows past I go to the spare row XR.
+template <int NSL, bool NORM>
+__device__ __forceinline__ void stash16(const View& v, int lane, int w, const uint32_t* pf,
+                                        bool ok, int XR, __bf16* Xb, double& nsum) {
+  const int I = (int)v.I;
+  const uint32_t keep = ok ? 0xffffffffu : 0u;
+  double ns[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < NSL; ++k) {
+    const int ii = 32 * k + 4 * w + (lane >> 4);
+    const int row = ii < I ? ii : XR;
+    const uint4 x = make_uint4(pf[4 * k] & keep, pf[4 * k + 1] & keep, pf[4 * k + 2] & keep,
+                               pf[4 * k + 3] & keep);
+    *(uint4*)(Xb + xidx(row, 8 * (lane & 15))) = x;
+    if (NORM && ii < I) {
+      const uint32_t d[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float lo = bf16_to_f32((bf16_t)(d[e] & 0xffffu)), hi = bf16_to_f32((bf16_t)(d[e] >> 16));
+        ns[e] += (double)lo * (double)lo + (double)hi * (double)hi;
+      }
+    }
+  }
+  if (NORM) nsum += (ns[0] + ns[1]) + (ns[2] + ns[3]);
+}
+
 // MODE 0: sweep; 2: init (sketch, norm, no Gram); 3: TTM.  NS: BF16 terms of
 // Lq in the R-update (1 when the Lq values are BF16-representable, else 3).
 template <int NR, int MODE, int IC, int NS>
@@ -423,7 +476,8 @@ __host__ __device__ inline LdsB lds_b16r(int IC, int NR, int mode) {
   return l;
 }
 
-template <int NR, int MODE, int IC, int NS>
+// V16: the 16-byte prefetch form (else one dword of two fibres per slot).
+template <int NR, int MODE, int IC, int NS, bool V16>
 __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   constexpr int RP = 16 * NR;
@@ -507,13 +561,28 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
   bool ok0 = false, ok1 = false;
   int64_t tile = blockIdx.x;
   int cur = 0;
+  auto fetch = [&](int64_t j0, uint32_t (&pf)[ICR], bool& ok) __attribute__((always_inline)) {
+    if constexpr (V16) prefetch16<XR / 32>((const uint4*)a.X, v, j0, lane, w, pf, ok);
+    else prefetch<ICR>(X2, v, j0, lane, w, pf, ok);
+  };
+  // stage a register buffer into tile buffer `buf`
+  auto put = [&](const uint32_t (&pf)[ICR], bool ok, int buf) __attribute__((always_inline)) {
+    if constexpr (V16) {
+      __bf16* Xb = Xs + buf * xbuf;
+      if (want_norm) stash16<XR / 32, true>(v, lane, w, pf, ok, XR, Xb, nsum);
+      else stash16<XR / 32, false>(v, lane, w, pf, ok, XR, Xb, nsum);
+    } else {
+      uint32_t* Xb32 = Xs32 + buf * (xbuf >> 1);
+      if (want_norm) stash<ICR, true>(v, lane, w, pf, ok, XR, Xb32, nsum);
+      else stash<ICR, false>(v, lane, w, pf, ok, XR, Xb32, nsum);
+    }
+  };
   __syncthreads();
   if (tile < ntiles) {
-    prefetch<ICR>(X2, v, tile * TJ, lane, w, pf0, ok0);
-    if (want_norm) stash<ICR, true>(v, lane, w, pf0, ok0, XR, Xs32, nsum);
-    else stash<ICR, false>(v, lane, w, pf0, ok0, XR, Xs32, nsum);
-    prefetch<ICR>(X2, v, (tile + nwg) * TJ, lane, w, pf0, ok0);
-    if (DB) prefetch<ICR>(X2, v, (tile + 2 * nwg) * TJ, lane, w, pf1, ok1);
+    fetch(tile * TJ, pf0, ok0);
+    put(pf0, ok0, 0);
+    fetch((tile + nwg) * TJ, pf0, ok0);
+    if (DB) fetch((tile + 2 * nwg) * TJ, pf1, ok1);
   }
   __syncthreads();
 
@@ -580,13 +649,11 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
     {
       // the next tile (zeros past the end; a duplicate norm term cannot
       // arise: lanes past the end add nothing)
-      uint32_t* Xn32 = Xs32 + (cur ^ 1) * (xbuf >> 1);
-      if (want_norm) stash<ICR, true>(v, lane, w, pf, pf_ok, XR, Xn32, nsum);
-      else stash<ICR, false>(v, lane, w, pf, pf_ok, XR, Xn32, nsum);
+      put(pf, pf_ok, cur ^ 1);
       const int64_t ahead = tile + (NB + 1) * (int64_t)nwg;
       // (past the end of the tensor by at most (NB + 1) nwg tiles: the
       // clamp keeps the fibre index valid)
-      prefetch<ICR>(X2, v, (ahead < ntiles ? ahead : ntiles) * TJ, lane, w, pf, pf_ok);
+      fetch((ahead < ntiles ? ahead : ntiles) * TJ, pf, pf_ok);
     }
     __syncthreads();
 
@@ -705,9 +772,15 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
 template <int NR, int MODE, int IC, int NS>
 void launch3r(const FusedArgs& a, int nwg, hipStream_t s) {
   const size_t bytes = (size_t)lds_b16r(IC, NR, MODE).total;
-  (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC, NS>,
+  if (a.v.Q % 8 == 0 && ((uintptr_t)a.X & 15) == 0) {
+    (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC, NS, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC, NS, true>), dim3(nwg), dim3(NT), bytes, s, a);
+    return;
+  }
+  (void)hipFuncSetAttribute((const void*)k_fused_bf16r<NR, MODE, IC, NS, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC, NS>), dim3(nwg), dim3(NT), bytes, s, a);
+  hipLaunchKernelGGL((k_fused_bf16r<NR, MODE, IC, NS, false>), dim3(nwg), dim3(NT), bytes, s, a);
 }
 
 template <int NR, int MODE, int IC, int NS>

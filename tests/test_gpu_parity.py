@@ -512,6 +512,9 @@ KERNEL_CASES = [
     ((6, 1, 16), 1, 1),         # I = 1, R = 1
     ((1, 150, 4), 1, 4),        # J = 4: one group of four fibres
     ((40, 200, 1004), 1, 20),   # 627.5 tiles: both prefetch buffers cycle, ragged end
+    # Q a multiple of 8: the BF16 16-byte prefetch form
+    ((40, 200, 1000), 1, 20),   # 312.5 BF16 tiles: both buffers cycle, ragged end
+    ((24, 200, 40), 1, 9),      # Q = 40 < one BF16 tile: tiles straddle p
 ]
 
 
