@@ -18,13 +18,14 @@
 //
 // Work layout: 256 persistent workgroups of 8 waves walk tiles of TJ = 128
 // fibres (view [P, I, Q] with Q even: each lane loads one dword holding two
-// adjacent fibres of a row).  The tile is kept in LDS as BF16 rows whose
-// 16-byte chunks are XOR-swizzled by row, so the eight-row column gathers
-// of the R-update hit distinct banks while the L-update reads contiguous
-// 16-byte runs of fibres.
+// adjacent fibres of a row; the register-resident variant below loads
+// eight adjacent fibres, 16 bytes, when Q is a multiple of 8).  The tile is
+// kept in LDS as BF16 rows whose 16-byte chunks are XOR-swizzled by row;
+// the L-update reads contiguous 16-byte runs of fibres.
 //   R-update  wave w owns fibre block w (16 fibres) for every rank tile:
-//             v_mfma_f32_16x16x32_bf16, A = X^T gathered (16 fibres x 32
-//             rows), B = Lq^T splits (32 rows x 16 ranks), K = 32-row stages;
+//             v_mfma_f32_16x16x32_bf16, A = X^T (16 fibres x 32 rows, two
+//             transposing LDS reads per operand), B = Lq^T splits (32 rows x
+//             16 ranks), K = 32-row stages;
 //   L-update  wave w owns row tiles w + 8 rt for every rank tile:
 //             v_mfma_f32_16x16x32_bf16, A = X (16 rows x 32 fibres), B = V
 //             splits (32 fibres x 16 ranks), K = the 128 fibres;
