@@ -651,11 +651,17 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
       // the next tile (zeros past the end; a duplicate norm term cannot
       // arise: lanes past the end add nothing)
       put(pf, pf_ok, cur ^ 1);
-      const int64_t ahead = tile + (NB + 1) * (int64_t)nwg;
-      // (past the end of the tensor by at most (NB + 1) nwg tiles: the
-      // clamp keeps the fibre index valid)
-      fetch((ahead < ntiles ? ahead : ntiles) * TJ, pf, pf_ok);
     }
+    // The buffer just staged fetches the tile NB + 1 steps ahead (past the
+    // end of the tensor by at most (NB + 1) nwg tiles: the clamp keeps the
+    // fibre index valid).  The older half of the waves issues its loads
+    // here; in the sweep and the TTM the younger half, whose issue would
+    // queue behind theirs, issues at the end of phase B (the buffer is next
+    // staged NB tiles later).  The init pass's phase B is the same L-update
+    // on every wave, so there all waves issue here.
+    const int64_t ahead = tile + (NB + 1) * (int64_t)nwg;
+    const bool early = MODE == 2 || w < NW / 2;
+    if (early) fetch((ahead < ntiles ? ahead : ntiles) * TJ, pf, pf_ok);
     __syncthreads();
 
     // ---- phase B
@@ -715,6 +721,7 @@ __global__ void __launch_bounds__(NT, 1) k_fused_bf16r(FusedArgs a) {
         for (int q = 0; q < 4; ++q) gd[q] += (double)g[q];
       }
     }
+    if (!early) fetch((ahead < ntiles ? ahead : ntiles) * TJ, pf, pf_ok);
     __syncthreads();
     cur ^= 1;
   };
