@@ -55,6 +55,9 @@ TTM_CASES = [
     ((33, 700), 1, 20, False),      # large-mode TTM, Q == 1
     ((9, 70, 40), 1, 19, True),     # TTM width 16 < J <= 20
     ((33, 60), 1, 17, False),       # TTM width 16 < J <= 20, Q == 1
+    # Q a multiple of 8, I <= 224: the BF16 16-byte prefetch form
+    ((6, 200, 48), 1, 20, True),    # tiles straddle p
+    ((3, 128, 1000), 1, 16, False), # 23.4 BF16 tiles, ragged end
 ]
 
 
@@ -152,14 +155,10 @@ INIT_LARGE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("dt", ["f32", "bf16"])
-@pytest.mark.parametrize("dims,mode,R", INIT_LARGE_CASES)
-def test_init_step_parity_large(gpu_lib, dims, mode, R, dt):
-    """Initial sketch pass (Section 5) on large modes: Y = A_(n) S and ||A||^2
-    against FP64 on the same stored values (FP32 accumulation of up to J
-    products per entry), and L_0 the QR of Y."""
-    tk = gpu_lib
-    flush(f"init large {dims} mode={mode} R={R} {dt}")
+def check_init_step(tk, dims, mode, R, dt):
+    """Initial sketch pass (Section 5): Y = A_(n) S and ||A||^2 against FP64
+    on the same stored values (FP32 accumulation of up to J products per
+    entry), and L_0 the QR of Y."""
     rng = np.random.default_rng(17)
     A = rng.standard_normal(dims)
     seed = 99
@@ -174,6 +173,31 @@ def test_init_step_parity_large(gpu_lib, dims, mode, R, dt):
     np.testing.assert_allclose(Q.T @ Q, np.eye(R), atol=1e-12)
     Qo, _ = o.qr_signfix(np64(Y))
     np.testing.assert_allclose(Q, Qo, atol=1e-10)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("dims,mode,R", INIT_LARGE_CASES)
+def test_init_step_parity_large(gpu_lib, dims, mode, R, dt):
+    """The sketch pass on large modes (chunked kernels)."""
+    flush(f"init large {dims} mode={mode} R={R} {dt}")
+    check_init_step(gpu_lib, dims, mode, R, dt)
+
+
+# BF16 storage on modes of up to 224 rows (the register-buffered BF16 kernel)
+INIT_BF16_CASES = [
+    ((40, 200, 48), 1, 20),     # Q = 48: 16-byte loads, tiles straddle p
+    ((6, 200, 1000), 1, 20),    # Q = 1000: 16-byte loads, 46.9 tiles, ragged end
+    ((200, 40, 30), 0, 16),     # P == 1, Q = 1200, one rank tile
+    ((9, 100, 64), 1, 30),      # I = 100, two rank tiles, Q = 64
+    ((20, 200, 50), 1, 20),     # Q = 50: dword loads
+]
+
+
+@pytest.mark.parametrize("dims,mode,R", INIT_BF16_CASES)
+def test_init_step_parity_bf16(gpu_lib, dims, mode, R):
+    """The sketch pass with BF16 storage on modes of up to 224 rows."""
+    flush(f"init bf16 {dims} mode={mode} R={R}")
+    check_init_step(gpu_lib, dims, mode, R, "bf16")
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
